@@ -1,0 +1,222 @@
+// Device building blocks shared by the library's kernels: the counter-based random numbers of
+// the common-random-numbers contract, and workgroup reductions and scans for 64-lane waves.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc2 {
+
+// Random streams of the counter contract: counter word 3 = (k << 8) | stream.
+enum : uint32_t {
+  kStreamInit = 1,      // x_0 normals, per particle slot
+  kStreamStep = 2,      // propagation normals, per particle slot, index (t-1)*d + q
+  kStreamResample = 3,  // resampling uniforms: systematic one per filter (slot word all ones),
+                        // multinomial one per offspring slot; index t-1
+  kStreamPrior = 4,     // theta_1 ~ prior, per sample, iteration 1
+  kStreamMove = 5,      // Langevin / random-walk move normals, per sample
+  kStreamOuter = 6      // outer systematic resampling uniform, per series
+};
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kHalfLog2Pi = 0.91893853320467274178032973640562;
+
+__device__ __forceinline__ uint32_t stream_word(uint32_t k, uint32_t stream) {
+  return (k << 8) | stream;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds; in each, words 0 and 2 are
+// multiplied (32x32 -> 64) by the two round multipliers, the high halves are mixed with words
+// 1 and 3 and the round key, and the key advances by the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint64_t seed) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// Box-Muller (Box & Muller 1958) on one word pair: u1 = (wa + 1) 2^-32 in (0, 1],
+// u2 = wb 2^-32 in [0, 1); z0 = r cos(2 pi u2), z1 = r sin(2 pi u2), r = sqrt(-2 ln u1).
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &z0, double &z1) {
+  const double u1 = ((double)wa + 1.0) * 0x1p-32;
+  const double u2 = (double)wb * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincos(kTwoPi * u2, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &z0, float &z1) {
+  const float u1 = ((float)wa + 1.0f) * 0x1p-32f;
+  const float u2 = (float)wb * 0x1p-32f;
+  const float r = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+// The four normals of one Philox block (pairs 2b and 2b+1 of the stream).
+template <typename R>
+__device__ __forceinline__ void normals4(uint32_t c0, uint32_t block, uint32_t c2, uint32_t c3,
+                                         uint64_t seed, R z[4]) {
+  const uint4 w = philox4x32_10(c0, block, c2, c3, seed);
+  box_muller(w.x, w.y, z[0], z[1]);
+  box_muller(w.z, w.w, z[2], z[3]);
+}
+
+// Normal number n of a stream (pair n/2 in block n/4).
+template <typename R>
+__device__ __forceinline__ R normal_n(uint32_t c0, uint32_t c2, uint32_t c3, uint32_t n,
+                                      uint64_t seed) {
+  const uint32_t p = n >> 1;
+  const uint4 w = philox4x32_10(c0, p >> 1, c2, c3, seed);
+  R z0, z1;
+  if (p & 1u)
+    box_muller(w.z, w.w, z0, z1);
+  else
+    box_muller(w.x, w.y, z0, z1);
+  return (n & 1u) ? z1 : z0;
+}
+
+// Uniform number m in (0, 1] of a stream: block m/4, word m%4, (w + 1) 2^-32 (exact in FP64).
+__device__ __forceinline__ double uniform_m(uint32_t c0, uint32_t c2, uint32_t c3, uint32_t m,
+                                            uint64_t seed) {
+  const uint4 w = philox4x32_10(c0, m >> 2, c2, c3, seed);
+  const uint32_t q = m & 3u;
+  const uint32_t v = q == 0 ? w.x : q == 1 ? w.y : q == 2 ? w.z : w.w;
+  return ((double)v + 1.0) * 0x1p-32;
+}
+
+// ---- wave and workgroup reductions ------------------------------------------------------------
+// Butterfly (xor) reductions: every lane combines the same two operands in the same order at
+// each stage (addition is commutative), so all 64 lanes end with bit-identical results.  The
+// cross-wave stage reads the per-wave values in wave order, so the workgroup result is also
+// identical in every thread, which keeps data-dependent branches uniform.
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int WAVES>
+__device__ __forceinline__ double block_max(double v, double *red) {
+  v = wave_max(v);
+  if constexpr (WAVES > 1) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    v = red[0];
+#pragma unroll
+    for (int w = 1; w < WAVES; ++w) v = fmax(v, red[w]);
+  }
+  return v;
+}
+
+template <int WAVES>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if constexpr (WAVES > 1) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[2 * wid] = a;
+      red[2 * wid + 1] = b;
+    }
+    __syncthreads();
+    a = red[0];
+    b = red[1];
+#pragma unroll
+    for (int w = 1; w < WAVES; ++w) {
+      a += red[2 * w];
+      b += red[2 * w + 1];
+    }
+  }
+}
+
+// Sum of D values per thread over the workgroup (D <= 32); result valid in every thread.
+template <int WAVES, int D>
+__device__ __forceinline__ void block_sum_vec(double *v, double *red) {
+#pragma unroll
+  for (int p = 0; p < D; ++p) v[p] = wave_sum(v[p]);
+  if constexpr (WAVES > 1) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int p = 0; p < D; ++p) red[wid * D + p] = v[p];
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      double s = red[p];
+      for (int w = 1; w < WAVES; ++w) s += red[w * D + p];
+      v[p] = s;
+    }
+  }
+}
+
+// Exclusive scan over the workgroup of one value per thread (thread order); returns the
+// exclusive prefix and sets `total` (identical in all threads).
+template <int WAVES>
+__device__ __forceinline__ double block_exclusive_scan(double v, double *wsum, double &total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double n = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += n;
+  }
+  double exc = __shfl_up(inc, 1, 64);
+  if (lane == 0) exc = 0.0;
+  if constexpr (WAVES == 1) {
+    total = __shfl(inc, 63, 64);
+    return exc;
+  } else {
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    double off = 0.0, tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      const double s = wsum[w];
+      if (w < wid) off += s;
+      tot += s;
+    }
+    total = tot;
+    return off + exc;
+  }
+}
+
+// Number of entries of the non-decreasing array P[0..n) that are < target, i.e. the lower
+// bound of target; fixed trip count for uniform control flow.
+__device__ __forceinline__ int lower_bound_lds(const double *P, int n, double target) {
+  int pos = 0;
+  int step = 1;
+  while ((step << 1) <= n) step <<= 1;
+  for (; step > 0; step >>= 1) {
+    const int probe = pos + step;
+    if (probe <= n && P[probe - 1] < target) pos = probe;
+  }
+  return pos;
+}
+
+}  // namespace smc2

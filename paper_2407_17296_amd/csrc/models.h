@@ -1,0 +1,175 @@
+// The state-space models of the library (paper eqs. xt and yt), each with the pieces the fused
+// filter kernel needs: the initial draw, the reparameterised bootstrap transition
+// x_t = mu(x_{t-1}, theta) + sqrt(C(theta)) e_t (eq. reparam_epsilon), the observation
+// log-density lambda = log g(y_t | x_t, theta), and the transposed (adjoint) forms of their
+// derivatives (App. A, eqs. deriv_loglike and df..dxk, transposed).
+//
+// R is the arithmetic type of propagation and weighting (double in the plain FP64 form, float
+// in the mixed form).  Parameters arrive in FP64 and are transformed once in FP64.  Gradient
+// contributions are accumulated into FP64 accumulators `tb` indexed like theta.
+#pragma once
+
+#include "device_common.h"
+
+namespace smc2 {
+
+// x_t = a x + sx e;  y = x + sy w;  theta = (a, log sx, log sy);  x_0 ~ N(0, 1).
+template <typename R>
+struct ModelLG1D {
+  static constexpr int DX = 1, NP = 3;
+  R a, sx, lsy, isy;
+  __device__ void setup(const double *th) {
+    a = (R)th[0];
+    sx = (R)exp(th[1]);
+    lsy = (R)th[2];
+    isy = (R)exp(-th[2]);
+  }
+  __device__ void per_step(int) {}
+  __device__ void init(const R *e0, R *x) const { x[0] = e0[0]; }
+  __device__ void init_adj(const R *, const R *, double *) const {}
+  __device__ void step(R *x, const R *e) const { x[0] = a * x[0] + sx * e[0]; }
+  // reverse of step: tb += F_theta^T xb;  xb <- F_x^T xb   (xp = state before the step)
+  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
+    tb[0] += (double)(xb[0] * xp[0]);
+    tb[1] += (double)(xb[0] * (sx * e[0]));
+    xb[0] = a * xb[0];
+  }
+  __device__ R logg(const R *y, const R *x) const {
+    const R r = (y[0] - x[0]) * isy;
+    return (R)(-kHalfLog2Pi) - lsy - (R)0.5 * r * r;
+  }
+  // xb += wb d lambda/dx;  tb += wb d lambda/dtheta
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
+    const R r = (y[0] - x[0]) * isy;
+    xb[0] += wb * r * isy;
+    tb[2] += (double)(wb * (r * r - (R)1));
+  }
+};
+
+// x_t,q = A_q x_q + sx e_q;  y_q = x_q + sy w_q;  theta = (A_1..A_d, log sx, log sy);
+// x_0 ~ N(0, I).  A is diagonal, so the transition is elementwise.
+template <typename R, int D_X>
+struct ModelLGDiag {
+  static constexpr int DX = D_X, NP = D_X + 2;
+  R A[D_X], sx, lsy, isy;
+  __device__ void setup(const double *th) {
+#pragma unroll
+    for (int q = 0; q < D_X; ++q) A[q] = (R)th[q];
+    sx = (R)exp(th[D_X]);
+    lsy = (R)th[D_X + 1];
+    isy = (R)exp(-th[D_X + 1]);
+  }
+  __device__ void per_step(int) {}
+  __device__ void init(const R *e0, R *x) const {
+#pragma unroll
+    for (int q = 0; q < D_X; ++q) x[q] = e0[q];
+  }
+  __device__ void init_adj(const R *, const R *, double *) const {}
+  __device__ void step(R *x, const R *e) const {
+#pragma unroll
+    for (int q = 0; q < D_X; ++q) x[q] = A[q] * x[q] + sx * e[q];
+  }
+  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
+    R ssx = (R)0;
+#pragma unroll
+    for (int q = 0; q < D_X; ++q) {
+      tb[q] += (double)(xb[q] * xp[q]);
+      ssx += xb[q] * e[q];
+      xb[q] = A[q] * xb[q];
+    }
+    tb[D_X] += (double)(ssx * sx);
+  }
+  __device__ R logg(const R *y, const R *x) const {
+    R acc = (R)0;
+#pragma unroll
+    for (int q = 0; q < D_X; ++q) {
+      const R r = (y[q] - x[q]) * isy;
+      acc += (R)(-kHalfLog2Pi) - lsy - (R)0.5 * r * r;
+    }
+    return acc;
+  }
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
+    R s2 = (R)0;
+#pragma unroll
+    for (int q = 0; q < D_X; ++q) {
+      const R r = (y[q] - x[q]) * isy;
+      xb[q] += wb * r * isy;
+      s2 += r * r - (R)1;
+    }
+    tb[D_X + 1] += (double)(wb * s2);
+  }
+};
+
+// x_t = x/2 + 25 x/(1+x^2) + 8 cos(1.2 t) + sx e;  y = x^2/20 + sy w;
+// theta = (log sx, log sy);  x_0 ~ N(0, 1).
+template <typename R>
+struct ModelGrowth {
+  static constexpr int DX = 1, NP = 2;
+  R sx, lsy, isy, drive;
+  __device__ void setup(const double *th) {
+    sx = (R)exp(th[0]);
+    lsy = (R)th[1];
+    isy = (R)exp(-th[1]);
+    drive = (R)0;
+  }
+  // the deterministic forcing of step t, evaluated once per step in FP64
+  __device__ void per_step(int t) { drive = (R)(8.0 * cos(1.2 * (double)t)); }
+  __device__ void init(const R *e0, R *x) const { x[0] = e0[0]; }
+  __device__ void init_adj(const R *, const R *, double *) const {}
+  __device__ void step(R *x, const R *e) const {
+    const R v = x[0];
+    x[0] = (R)0.5 * v + (R)25 * v / ((R)1 + v * v) + drive + sx * e[0];
+  }
+  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
+    const R v = xp[0], den = (R)1 + v * v;
+    const R fx = (R)0.5 + (R)25 * ((R)1 - v * v) / (den * den);
+    tb[0] += (double)(xb[0] * (sx * e[0]));
+    xb[0] = fx * xb[0];
+  }
+  __device__ R logg(const R *y, const R *x) const {
+    const R r = (y[0] - x[0] * x[0] * (R)0.05) * isy;
+    return (R)(-kHalfLog2Pi) - lsy - (R)0.5 * r * r;
+  }
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
+    const R r = (y[0] - x[0] * x[0] * (R)0.05) * isy;
+    xb[0] += wb * r * isy * x[0] * (R)0.1;
+    tb[1] += (double)(wb * (r * r - (R)1));
+  }
+};
+
+// x_t = mu + phi (x - mu) + s e;  y = exp(x/2) w;  theta = (mu, atanh phi, log s);
+// x_0 ~ N(mu, s^2 / (1 - phi^2)) = mu + s cosh(theta_1) e_0.
+template <typename R>
+struct ModelSV {
+  static constexpr int DX = 1, NP = 3;
+  R mu, phi, s, sd0, dsd0;  // dsd0 = d sd0 / d theta_1 = s sinh(theta_1)
+  __device__ void setup(const double *th) {
+    mu = (R)th[0];
+    phi = (R)tanh(th[1]);
+    s = (R)exp(th[2]);
+    sd0 = (R)(exp(th[2]) * cosh(th[1]));
+    dsd0 = (R)(exp(th[2]) * sinh(th[1]));
+  }
+  __device__ void per_step(int) {}
+  __device__ void init(const R *e0, R *x) const { x[0] = mu + sd0 * e0[0]; }
+  __device__ void init_adj(const R *e0, const R *xb, double *tb) const {
+    tb[0] += (double)xb[0];
+    tb[1] += (double)(xb[0] * dsd0 * e0[0]);
+    tb[2] += (double)(xb[0] * sd0 * e0[0]);
+  }
+  __device__ void step(R *x, const R *e) const { x[0] = mu + phi * (x[0] - mu) + s * e[0]; }
+  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
+    tb[0] += (double)(xb[0] * ((R)1 - phi));
+    tb[1] += (double)(xb[0] * ((R)1 - phi * phi) * (xp[0] - mu));
+    tb[2] += (double)(xb[0] * (s * e[0]));
+    xb[0] = phi * xb[0];
+  }
+  __device__ R logg(const R *y, const R *x) const {
+    return (R)(-kHalfLog2Pi) - (R)0.5 * x[0] - (R)0.5 * y[0] * y[0] * exp(-x[0]);
+  }
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *) const {
+    xb[0] += wb * ((R)(-0.5) + (R)0.5 * y[0] * y[0] * exp(-x[0]));
+  }
+};
+
+}  // namespace smc2

@@ -1,0 +1,222 @@
+// Kernels of the SMC^2 outer step (paper Sec. III) and small utilities.
+//   K2 langevin_move_kernel   -- proposal SMC1 (or SMC0), one thread per sample.
+//   K3 reweight_resample_kernel -- L-kernel weight, normalisation, ESS, systematic resampling,
+//                                  one workgroup per series.
+#pragma once
+
+#include "device_common.h"
+
+namespace smc2 {
+
+constexpr int kMaxD = 32;
+
+struct Prior {
+  double mu[kMaxD], sd[kMaxD];
+};
+
+// theta_1 ~ prior (eq. init_sample with q_1 = prior): one thread per (s, i).
+__global__ void prior_init_kernel(int n_items, int D, Prior pr, uint64_t seed, double *theta) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= n_items) return;
+  const uint32_t c3 = stream_word(1u, kStreamPrior);
+  for (int p = 0; p < D; ++p)
+    theta[(size_t)item * D + p] =
+        pr.mu[p] + pr.sd[p] * normal_n<double>(kNoSlot, (uint32_t)item, c3, (uint32_t)p, seed);
+}
+
+// K2: p_{k-1} = gamma xi, theta_new = theta + (gamma^2/2) grad_logpost + p_{k-1} (SMC1,
+// Sec. III-D, in the velocity form of Sec. III-E); SMC0 drops the gradient term.
+__global__ void langevin_move_kernel(int n_items, int D, double gamma, int random_walk,
+                                     const double *theta, const double *grad_logpost,
+                                     uint64_t seed, const uint32_t *iteration, double *theta_new,
+                                     double *p_prev) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= n_items) return;
+  const uint32_t c3 = stream_word(*iteration, kStreamMove);
+  const double half_g2 = 0.5 * gamma * gamma;
+  for (int b = 0; b * 4 < D; ++b) {
+    double z[4];
+    normals4<double>(kNoSlot, (uint32_t)b, (uint32_t)item, c3, seed, z);
+    for (int r = 0; r < 4 && 4 * b + r < D; ++r) {
+      const size_t o = (size_t)item * D + 4 * b + r;
+      const double pv = gamma * z[r];
+      p_prev[o] = pv;
+      theta_new[o] = random_walk ? theta[o] + pv : theta[o] + half_g2 * grad_logpost[o] + pv;
+    }
+  }
+}
+
+struct OuterArgs {
+  int S, N, D, first, random_walk;
+  double gamma;
+  Prior pr;
+  uint64_t seed;
+  const uint32_t *iteration;
+  double *theta, *logpost, *grad_logpost, *loglik, *logw;                // cur (in/out)
+  const double *prev_logpost, *prev_grad_logpost, *prev_logw, *p_prev;  // prev (k > 1)
+  int32_t *anc_out;
+  double *ess_out;
+  int32_t *resampled_out;
+  double *scratch;  // [S][N][2D+2] gather double buffer
+  int32_t *status;
+};
+
+// K3: one workgroup of OUTER_THREADS threads per series; each thread owns a contiguous block of
+// samples (N <= 4096).
+constexpr int kOuterThreads = 512;
+constexpr int kOuterMaxN = 4096;
+constexpr int kOuterPer = kOuterMaxN / kOuterThreads;
+
+__global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterArgs A) {
+  constexpr int WAVES = kOuterThreads / 64;
+  constexpr double kNegInf = -__builtin_huge_val();
+  __shared__ double sh_P[kOuterMaxN];
+  __shared__ double sh_red[2][2 * WAVES + 2];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int N = A.N, D = A.D;
+  const int per = (N + kOuterThreads - 1) / kOuterThreads;
+  const int i0 = tid * per;
+  const uint32_t k = *A.iteration;
+  const double g2 = A.gamma * A.gamma;
+
+  double lw[kOuterPer];
+  double mloc = kNegInf;
+  for (int r = 0; r < kOuterPer; ++r) {
+    lw[r] = kNegInf;
+    const int i = i0 + r;
+    if (r >= per || i >= N) continue;
+    const size_t it = (size_t)s * N + i;
+    double *th = A.theta + it * D;
+    double *g = A.grad_logpost + it * D;
+    // log pi = log p(theta) + loglik and grad log pi = grad log p + grad loglik
+    // (eqs. log_posterior, first_gradientlogposterior)
+    double lp = 0.0;
+    for (int p = 0; p < D; ++p) {
+      const double z = (th[p] - A.pr.mu[p]) / A.pr.sd[p];
+      lp += -kHalfLog2Pi - log(A.pr.sd[p]) - 0.5 * z * z;
+      g[p] += -z / A.pr.sd[p];
+    }
+    const double ll = A.loglik[it];
+    const double lpost = lp + ll;
+    A.logpost[it] = lpost;
+    double v;
+    if (A.first) {
+      v = ll;  // eq. init_weights with q_1 = prior
+    } else if (A.prev_logw[it] == kNegInf || lpost == kNegInf) {
+      v = kNegInf;
+    } else {
+      // eq. l_weights: w_k = w_{k-1} pi_k / pi_{k-1} L / q, with L / q = N(-p_k; 0, G) /
+      // N(p_{k-1}; 0, G) and p_k = p_{k-1} + F(theta_{k-1}) + F(theta_k) (Sec. III-E)
+      double inc = lpost - A.prev_logpost[it];
+      if (!A.random_walk) {
+        double npk = 0.0, npp = 0.0;
+        for (int p = 0; p < D; ++p) {
+          const double pp = A.p_prev[it * D + p];
+          const double pk = pp + 0.5 * g2 * (A.prev_grad_logpost[it * D + p] + g[p]);
+          npk += pk * pk;
+          npp += pp * pp;
+        }
+        inc += -(npk - npp) / (2.0 * g2);
+      }
+      v = A.prev_logw[it] + inc;
+    }
+    if (!(v == v)) v = kNegInf;
+    lw[r] = v;
+    A.logw[it] = v;
+    mloc = fmax(mloc, v);
+  }
+  const double mx = block_max<WAVES>(mloc, sh_red[0]);
+  double e[kOuterPer], S = 0.0, Q = 0.0;
+  for (int r = 0; r < kOuterPer; ++r) {
+    e[r] = (mx == kNegInf) ? 0.0 : exp(lw[r] - mx);
+    S += e[r];
+    Q += e[r] * e[r];
+  }
+  block_sum2<WAVES>(S, Q, sh_red[1]);
+  const double ess = (mx == kNegInf) ? 0.0 : S * S / Q;  // eqs. normalise_smc2, ess_smc2
+  const bool res = mx != kNegInf && ess < 0.5 * (double)N;
+  if (tid == 0) {
+    if (A.ess_out) A.ess_out[s] = ess;
+    if (A.resampled_out) A.resampled_out[s] = res ? 1 : 0;
+    if (mx == kNegInf) *A.status = 5;  // every weight of this series is zero
+  }
+  if (!res) {
+    if (A.anc_out)
+      for (int r = 0; r < per; ++r)
+        if (i0 + r < N) A.anc_out[(size_t)s * N + i0 + r] = i0 + r;
+    return;
+  }
+  // systematic resampling: inclusive FP64 prefix, lower bound of (i + nu)/N * total
+  double acc = 0.0, pre[kOuterPer];
+  for (int r = 0; r < kOuterPer; ++r) {
+    acc += e[r];
+    pre[r] = acc;
+  }
+  double tot;
+  const double off = block_exclusive_scan<WAVES>(acc, sh_red[0], tot);
+  for (int r = 0; r < per; ++r)
+    if (i0 + r < N) sh_P[i0 + r] = off + pre[r];
+  const double nu = uniform_m(kNoSlot, (uint32_t)s, stream_word(k, kStreamOuter), 0u, A.seed);
+  __syncthreads();
+  const double total = sh_P[N - 1];
+  const double lse = mx + log(S);
+  const int W = 2 * D + 2;
+  for (int r = 0; r < per; ++r) {
+    const int i = i0 + r;
+    if (i >= N) continue;
+    const int a = min(lower_bound_lds(sh_P, N, ((double)i + nu) / (double)N * total), N - 1);
+    if (A.anc_out) A.anc_out[(size_t)s * N + i] = a;
+    const size_t src = (size_t)s * N + a, dst = (size_t)s * N + i;
+    double *sc = A.scratch + dst * W;
+    for (int p = 0; p < D; ++p) {
+      sc[p] = A.theta[src * D + p];
+      sc[D + p] = A.grad_logpost[src * D + p];
+    }
+    sc[2 * D] = A.logpost[src];
+    sc[2 * D + 1] = A.loglik[src];
+  }
+  __syncthreads();  // every read of the old population precedes the in-place writes
+  for (int r = 0; r < per; ++r) {
+    const int i = i0 + r;
+    if (i >= N) continue;
+    const size_t dst = (size_t)s * N + i;
+    const double *sc = A.scratch + dst * W;
+    for (int p = 0; p < D; ++p) {
+      A.theta[dst * D + p] = sc[p];
+      A.grad_logpost[dst * D + p] = sc[D + p];
+    }
+    A.logpost[dst] = sc[2 * D];
+    A.loglik[dst] = sc[2 * D + 1];
+    A.logw[dst] = lse - log((double)N);  // equal, sum-preserving weights after resampling
+  }
+}
+
+__global__ void advance_iteration_kernel(uint32_t *iteration) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *iteration = *iteration + 1u;
+}
+
+__global__ void reset_queue_kernel(uint32_t *queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
+}
+
+// Counter-contract probe.
+__global__ void philox_probe_kernel(int R, const uint32_t *ctr, const uint32_t *n, uint64_t seed,
+                                    uint32_t *out, double *normals, double *uniforms,
+                                    float *normals32, float *uniforms32) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const uint32_t c0 = ctr[4 * r], c1 = ctr[4 * r + 1], c2 = ctr[4 * r + 2], c3 = ctr[4 * r + 3];
+  if (out) {
+    const uint4 w = philox4x32_10(c0, c1, c2, c3, seed);
+    out[4 * r] = w.x;
+    out[4 * r + 1] = w.y;
+    out[4 * r + 2] = w.z;
+    out[4 * r + 3] = w.w;
+  }
+  if (normals) normals[r] = normal_n<double>(c0, c2, c3, n[r], seed);
+  if (normals32) normals32[r] = normal_n<float>(c0, c2, c3, n[r], seed);
+  if (uniforms) uniforms[r] = uniform_m(c0, c2, c3, n[r], seed);
+  if (uniforms32) uniforms32[r] = (float)uniform_m(c0, c2, c3, n[r], seed);
+}
+
+}  // namespace smc2
