@@ -91,6 +91,31 @@ double uniform_m(uint64_t seed, uint32_t c0, uint32_t c2, uint32_t c3, uint32_t 
 
 uint32_t c3_of(uint32_t k, uint32_t stream) { return (k << 8) | stream; }
 
+/* Per-filter noise of one step (t >= 1) or of the initial draw (t = 0): element g = j*d + q
+ * (slot j, component q) is normal number g % 4 of block (c0 = g / 4, c1 = t), i.e. Box-Muller
+ * pair (g % 4) / 2 of that block, cosine branch for even g.  One generator block serves four
+ * consecutive elements of the same step. */
+double filter_normal(uint64_t seed, uint32_t fid, uint32_t c3, uint32_t t, uint32_t g) {
+  uint32_t w[4];
+  block_words(seed, g >> 2, t, fid, c3, w);
+  uint32_t pr = (g & 3u) >> 1;
+  double u1 = ((double)w[2 * pr] + 1.0) * 0x1p-32;
+  double u2 = (double)w[2 * pr + 1] * 0x1p-32;
+  double r = std::sqrt(-2.0 * std::log(u1));
+  double ang = kTwoPi * u2;
+  return (g & 1u) ? r * std::sin(ang) : r * std::cos(ang);
+}
+
+/* Per-filter resampling uniform of step t: offspring slot i uses word i % 4 of block
+ * (c0 = i / 4, c1 = t) (multinomial); the systematic offset uses word 0 of block
+ * (c0 = 0xFFFFFFFF, c1 = t). */
+double filter_uniform(uint64_t seed, uint32_t fid, uint32_t c3, uint32_t t, uint32_t c0,
+                      uint32_t word) {
+  uint32_t w[4];
+  block_words(seed, c0, t, fid, c3, w);
+  return ((double)w[word & 3u] + 1.0) * 0x1p-32;
+}
+
 /* ---------------- real/complex helpers ------------------------------------------------------- */
 
 inline double re(double v) { return v; }
@@ -319,7 +344,7 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
                  c3_res = c3_of(k, ORC_RESAMPLE_UNIFORM);
   const double lWeq = -std::log((double)M);
   for (int j = 0; j < M; ++j) {
-    for (int q = 0; q < d; ++q) eps[q] = normal_n(seed, (uint32_t)j, fid, c3_init, (uint32_t)q);
+    for (int q = 0; q < d; ++q) eps[q] = filter_normal(seed, fid, c3_init, 0u, (uint32_t)(j * d + q));
     mod.init(eps.data(), &x[(size_t)j * d], tangent ? &dx[(size_t)j * d * D] : nullptr);
     lW[j] = R(lWeq);
   }
@@ -331,7 +356,7 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
     /* propagate with the bootstrap proposal and weight by g (eq. priorproposalweight) */
     for (int j = 0; j < M; ++j) {
       for (int q = 0; q < d; ++q)
-        eps[q] = normal_n(seed, (uint32_t)j, fid, c3_step, (uint32_t)((t - 1) * d + q));
+        eps[q] = filter_normal(seed, fid, c3_step, (uint32_t)t, (uint32_t)(j * d + q));
       double *dxj = tangent ? &dx[(size_t)j * d * D] : nullptr;
       mod.propagate(t, &x[(size_t)j * d], eps.data(), dxj);
       R lam = mod.logg(yt, &x[(size_t)j * d], tangent ? dl_dx.data() : nullptr,
@@ -386,10 +411,11 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
     double ess = Sre * Sre / Q;
     if (t < T && ess < opt->ess_frac * (double)M) {
       if (opt->resampler == ORC_SYSTEMATIC) {
-        double nu = uniform_m(seed, 0xFFFFFFFFu, fid, c3_res, (uint32_t)(t - 1));
+        double nu = filter_uniform(seed, fid, c3_res, (uint32_t)t, 0xFFFFFFFFu, 0u);
         for (int i = 0; i < M; ++i) u[i] = ((double)i + nu) / (double)M;
       } else {
-        for (int i = 0; i < M; ++i) u[i] = uniform_m(seed, (uint32_t)i, fid, c3_res, (uint32_t)(t - 1));
+        for (int i = 0; i < M; ++i)
+          u[i] = filter_uniform(seed, fid, c3_res, (uint32_t)t, (uint32_t)i >> 2, (uint32_t)i & 3u);
       }
       lower_bound_ancestors(M, e.data(), u.data(), a.data());
       /* x'_i = x_{kappa_i}; dx'_i = dx_{kappa_i} almost surely; equal sum-preserving weights, whose
@@ -465,6 +491,15 @@ void orc_normals(uint64_t seed, uint32_t c0, uint32_t c2, uint32_t c3, uint32_t 
 void orc_uniforms(uint64_t seed, uint32_t c0, uint32_t c2, uint32_t c3, uint32_t first,
                   int64_t count, double *out) {
   for (int64_t i = 0; i < count; ++i) out[i] = uniform_m(seed, c0, c2, c3, first + (uint32_t)i);
+}
+
+double orc_filter_normal(uint64_t seed, uint32_t fid, uint32_t c3, uint32_t t, uint32_t g) {
+  return filter_normal(seed, fid, c3, t, g);
+}
+
+double orc_filter_uniform(uint64_t seed, uint32_t fid, uint32_t c3, uint32_t t, uint32_t c0,
+                          uint32_t word) {
+  return filter_uniform(seed, fid, c3, t, c0, word);
 }
 
 void orc_resample_lower_bound(int32_t M, const double *w, const double *u, int32_t *a) {

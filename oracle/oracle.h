@@ -11,7 +11,12 @@
  * Conventions (both sides implement them independently, see the counter contract in the design
  * notes):
  *   - Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), key = (lo32(seed), hi32(seed)),
- *     counter = (c0 = slot or 0xFFFFFFFF, c1 = block, c2 = filter id, c3 = (k << 8) | stream).
+ *     counter = (c0, c1, c2 = filter id or series, c3 = (k << 8) | stream).
+ *   - Filter noise: element g = j*d + q of step t (t = 0: the initial draw) is normal g % 4 of
+ *     block (c0 = g / 4, c1 = t); resampling uniforms of step t: word i % 4 of block
+ *     (i / 4, t) per offspring (multinomial), word 0 of block (0xFFFFFFFF, t) (systematic).
+ *   - Per-sample streams (prior, move, outer resampling): c0 = 0xFFFFFFFF, normal n in block
+ *     n / 4 (c1), uniform m in block m / 4.
  *   - Box-Muller (Box & Muller 1958) on word pairs; uniforms (w + 1) * 2^-32 in (0, 1].
  *   - Arrays are row-major; y is [T][d]; theta is [D]; ancestors are [T][M] int32.
  */
@@ -53,6 +58,11 @@ void orc_normals(uint64_t seed, uint32_t c0, uint32_t c2, uint32_t c3, uint32_t 
                  int64_t count, double *out);
 void orc_uniforms(uint64_t seed, uint32_t c0, uint32_t c2, uint32_t c3, uint32_t first,
                   int64_t count, double *out);
+
+/* The filter's noise and resampling uniforms under the contract above. */
+double orc_filter_normal(uint64_t seed, uint32_t fid, uint32_t c3, uint32_t t, uint32_t g);
+double orc_filter_uniform(uint64_t seed, uint32_t fid, uint32_t c3, uint32_t t, uint32_t c0,
+                          uint32_t word);
 
 /* Resampling rule (paper App. B): given unnormalised weights w[M] and positions u[M] in (0, 1],
  * a[i] = first m with P_m >= u[i] * P_{M-1}, P the inclusive prefix sum of w. */

@@ -69,6 +69,10 @@ def lib():
         L.orc_uniform.restype = ctypes.c_double
         L.orc_normals.argtypes = [u64, u32, u32, u32, u32, i64, dp]
         L.orc_uniforms.argtypes = [u64, u32, u32, u32, u32, i64, dp]
+        L.orc_filter_normal.argtypes = [u64, u32, u32, u32, u32]
+        L.orc_filter_normal.restype = ctypes.c_double
+        L.orc_filter_uniform.argtypes = [u64, u32, u32, u32, u32, u32]
+        L.orc_filter_uniform.restype = ctypes.c_double
         L.orc_resample_lower_bound.argtypes = [i32, dp, dp, ip]
         L.orc_pf.argtypes = [mp, op, dp, i32, dp, i32, u64, u32, u32, dp, dp, ip, u8p, dp]
         L.orc_pf.restype = ctypes.c_int

@@ -89,8 +89,8 @@ def test_T1_is_log_mean_of_likelihoods(oracle):
     y = np.array([[0.4]])
     x1 = []
     for j in range(M):
-        x0 = oracle.lib().orc_normal(seed, j, fid, oracle.c3(k, oracle.INIT_NORMAL), 0)
-        e1 = oracle.lib().orc_normal(seed, j, fid, oracle.c3(k, oracle.STEP_NORMAL), 0)
+        x0 = oracle.lib().orc_filter_normal(seed, fid, oracle.c3(k, oracle.INIT_NORMAL), 0, j)
+        e1 = oracle.lib().orc_filter_normal(seed, fid, oracle.c3(k, oracle.STEP_NORMAL), 1, j)
         x1.append(th[0] * x0 + np.exp(th[1]) * e1)
     g = stats.norm(np.array(x1), np.exp(th[2])).logpdf(0.4)
     want = np.log(np.mean(np.exp(g)))
@@ -104,10 +104,10 @@ def test_M1_is_single_path_likelihood(oracle):
     m = _model(oracle, w)
     th = np.array([0.3, -0.1])
     seed, k, fid = 5, 1, 0
-    x = oracle.lib().orc_normal(seed, 0, fid, oracle.c3(k, oracle.INIT_NORMAL), 0)
+    x = oracle.lib().orc_filter_normal(seed, fid, oracle.c3(k, oracle.INIT_NORMAL), 0, 0)
     ll = 0.0
     for t in range(1, 31):
-        e = oracle.lib().orc_normal(seed, 0, fid, oracle.c3(k, oracle.STEP_NORMAL), t - 1)
+        e = oracle.lib().orc_filter_normal(seed, fid, oracle.c3(k, oracle.STEP_NORMAL), t, 0)
         x = x / 2 + 25 * x / (1 + x * x) + 8 * np.cos(1.2 * t) + np.exp(th[0]) * e
         ll += stats.norm(x * x / 20, np.exp(th[1])).logpdf(w.y[0, t - 1, 0])
     r = oracle.pf(m, th, _y(w), 1, seed, k, fid, want_trace=True)
