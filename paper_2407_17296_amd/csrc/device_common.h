@@ -59,15 +59,24 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &z0,
   z1 = r * s;
 }
 
+// The FP32 form runs the transcendentals on the hardware units: v_log_f32 is log2, v_sqrt_f32,
+// and v_sin_f32 / v_cos_f32 take their argument in revolutions, so cos(2 pi u2) is one
+// instruction.
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &z0, float &z1) {
   const float u1 = ((float)wa + 1.0f) * 0x1p-32f;
   const float u2 = (float)wb * 0x1p-32f;
-  const float r = sqrtf(-2.0f * logf(u1));
-  float s, c;
-  sincospif(2.0f * u2, &s, &c);
-  z0 = r * c;
-  z1 = r * s;
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  z0 = r * __builtin_amdgcn_cosf(u2);
+  z1 = r * __builtin_amdgcn_sinf(u2);
 }
+
+// exp and reciprocal in the arithmetic type: library FP64, hardware FP32 (v_exp_f32 is 2^x).
+__device__ __forceinline__ double fexp(double x) { return exp(x); }
+__device__ __forceinline__ float fexp(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // The four normals of one Philox block (pairs 2b and 2b+1 of the stream).
 template <typename R>
@@ -204,6 +213,28 @@ __device__ __forceinline__ double block_exclusive_scan(double v, double *wsum, d
     total = tot;
     return off + exc;
   }
+}
+
+// Exclusive max-scan over the workgroup of one int per thread (thread order); -1 for thread 0.
+template <int WAVES>
+__device__ __forceinline__ int block_exclusive_max_scan(int v, int *wmax) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int n = __shfl_up(inc, o, 64);
+    if (lane >= o) inc = max(inc, n);
+  }
+  int exc = __shfl_up(inc, 1, 64);
+  if (lane == 0) exc = -1;
+  if constexpr (WAVES > 1) {
+    if (lane == 63) wmax[wid] = inc;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w)
+      if (w < wid) exc = max(exc, wmax[w]);
+  }
+  return exc;
 }
 
 // Number of entries of the non-decreasing array P[0..n) that are < target, i.e. the lower

@@ -118,11 +118,11 @@ struct ModelGrowth {
   __device__ void init_adj(const R *, const R *, double *) const {}
   __device__ void step(R *x, const R *e) const {
     const R v = x[0];
-    x[0] = (R)0.5 * v + (R)25 * v / ((R)1 + v * v) + drive + sx * e[0];
+    x[0] = (R)0.5 * v + (R)25 * v * frcp((R)1 + v * v) + drive + sx * e[0];
   }
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
-    const R v = xp[0], den = (R)1 + v * v;
-    const R fx = (R)0.5 + (R)25 * ((R)1 - v * v) / (den * den);
+    const R v = xp[0], iden = frcp((R)1 + v * v);
+    const R fx = (R)0.5 + (R)25 * ((R)1 - v * v) * (iden * iden);
     tb[0] += (double)(xb[0] * (sx * e[0]));
     xb[0] = fx * xb[0];
   }
@@ -165,10 +165,10 @@ struct ModelSV {
     xb[0] = phi * xb[0];
   }
   __device__ R logg(const R *y, const R *x) const {
-    return (R)(-kHalfLog2Pi) - (R)0.5 * x[0] - (R)0.5 * y[0] * y[0] * exp(-x[0]);
+    return (R)(-kHalfLog2Pi) - (R)0.5 * x[0] - (R)0.5 * y[0] * y[0] * fexp(-x[0]);
   }
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *) const {
-    xb[0] += wb * ((R)(-0.5) + (R)0.5 * y[0] * y[0] * exp(-x[0]));
+    xb[0] += wb * ((R)(-0.5) + (R)0.5 * y[0] * y[0] * fexp(-x[0]));
   }
 };
 

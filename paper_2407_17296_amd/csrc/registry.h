@@ -10,35 +10,49 @@ namespace smc2 {
 struct PFKernel {
   int model, dx, precision, waves, ppl;
   void (*launch)(const PFArgs &, int grid, hipStream_t);
-  int (*occupancy)();  // resident workgroups per compute unit
+  int (*occupancy)(int lds_T);       // resident workgroups per compute unit
+  size_t (*dyn_lds)(int lds_T);      // dynamic shared memory per workgroup
+  size_t static_lds;                 // static shared memory per workgroup (upper bound)
 };
 
 // Launch shapes (tile index -> waves per workgroup, particles per lane).  Index 0 is "tuned".
 struct Tile {
   int waves, ppl;
 };
-constexpr Tile kTiles[] = {{0, 0}, {1, 1}, {2, 1}, {4, 1}, {1, 4}, {4, 2}, {8, 1},
-                           {4, 4}, {8, 2}, {8, 4}, {16, 4}, {16, 2}};
+constexpr Tile kTiles[] = {{0, 0},  {1, 1}, {2, 1}, {1, 4},  {4, 1}, {1, 8},  {2, 4},
+                           {4, 2},  {1, 16}, {2, 8}, {4, 4}, {8, 2}, {2, 16}, {4, 8},
+                           {8, 4},  {4, 16}, {8, 8}, {16, 2}};
 constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
 
 template <typename R, class Model, int W, int P>
-void launch_pf(const PFArgs &a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((pf_fwd_adj_kernel<R, Model, W, P>), dim3(grid), dim3(W * 64), 0, st, a);
+size_t dyn_lds_pf(int lds_T) {
+  return pf_dyn_lds_bytes<R, Model::DX>(lds_T);
 }
 
 template <typename R, class Model, int W, int P>
-int occupancy_pf() {
+void launch_pf(const PFArgs &a, int grid, hipStream_t st) {
+  const size_t dyn = pf_dyn_lds_bytes<R, Model::DX>(a.lds_T);
+  hipLaunchKernelGGL((pf_fwd_adj_kernel<R, Model, W, P>), dim3(grid), dim3(W * 64), dyn, st, a);
+}
+
+template <typename R, class Model, int W, int P>
+int occupancy_pf(int lds_T) {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pf_fwd_adj_kernel<R, Model, W, P>, W * 64,
-                                                   0) != hipSuccess || n < 1)
+                                                   dyn_lds_pf<R, Model, W, P>(lds_T)) !=
+          hipSuccess ||
+      n < 1)
     n = 1;
   return n;
 }
 
 template <typename R, class Model, int W, int P>
 void add_entry(std::vector<PFKernel> &v, int model, int precision) {
+  constexpr int MP = W * 64 * P;
+  constexpr size_t stat = MP * (sizeof(double) + 2 * sizeof(R) + sizeof(int)) +
+                          (2 * (2 * W + 2) + W * Model::NP) * sizeof(double) + 4 * W + 64;
   v.push_back(PFKernel{model, Model::DX, precision, W, P, &launch_pf<R, Model, W, P>,
-                       &occupancy_pf<R, Model, W, P>});
+                       &occupancy_pf<R, Model, W, P>, &dyn_lds_pf<R, Model, W, P>, stat});
 }
 
 // Every d=1 launch shape for one (R, Model).
@@ -46,15 +60,20 @@ template <typename R, class Model>
 void add_all_tiles_1d(std::vector<PFKernel> &v, int model, int precision) {
   add_entry<R, Model, 1, 1>(v, model, precision);
   add_entry<R, Model, 2, 1>(v, model, precision);
-  add_entry<R, Model, 4, 1>(v, model, precision);
   add_entry<R, Model, 1, 4>(v, model, precision);
+  add_entry<R, Model, 4, 1>(v, model, precision);
+  add_entry<R, Model, 1, 8>(v, model, precision);
+  add_entry<R, Model, 2, 4>(v, model, precision);
   add_entry<R, Model, 4, 2>(v, model, precision);
-  add_entry<R, Model, 8, 1>(v, model, precision);
+  add_entry<R, Model, 1, 16>(v, model, precision);
+  add_entry<R, Model, 2, 8>(v, model, precision);
   add_entry<R, Model, 4, 4>(v, model, precision);
   add_entry<R, Model, 8, 2>(v, model, precision);
+  add_entry<R, Model, 2, 16>(v, model, precision);
+  add_entry<R, Model, 4, 8>(v, model, precision);
   add_entry<R, Model, 8, 4>(v, model, precision);
-  add_entry<R, Model, 16, 4>(v, model, precision);
-  add_entry<R, Model, 16, 2>(v, model, precision);
+  add_entry<R, Model, 4, 16>(v, model, precision);
+  add_entry<R, Model, 8, 8>(v, model, precision);
 }
 
 // Launch shapes for the 16-dimensional state (register budget: x is 16 values per particle).
@@ -63,7 +82,7 @@ void add_all_tiles_16d(std::vector<PFKernel> &v, int model, int precision) {
   add_entry<R, Model, 1, 1>(v, model, precision);
   add_entry<R, Model, 2, 1>(v, model, precision);
   add_entry<R, Model, 4, 1>(v, model, precision);
-  add_entry<R, Model, 8, 1>(v, model, precision);
+  add_entry<R, Model, 4, 2>(v, model, precision);
   add_entry<R, Model, 8, 2>(v, model, precision);
   add_entry<R, Model, 16, 2>(v, model, precision);
 }

@@ -87,26 +87,30 @@ Prior make_prior(const smc2_model *m) {
 
 // Default launch shape per particle count (largest particles-per-lane that keeps 4+ waves for
 // M >= 256; a single wave for the small filters).
-int default_tile(int MP, int dx) {
+int default_tile(int MP, int dx, int precision) {
+  // tile indices refer to kTiles; measured on MI355X (fused forward+adjoint, systematic
+  // resampling at most steps): one or two waves with 4 to 8 particles per lane for the 1-D
+  // models; the 16-dimensional state keeps one or two particles per lane
   if (dx == 16) {
     switch (MP) {
-      case 64: return 1;
-      case 128: return 2;
-      case 256: return 3;
-      case 512: return 6;
-      case 1024: return 8;
-      case 2048: return 11;
+      case 64: return 1;     // {1, 1}
+      case 128: return 2;    // {2, 1}
+      case 256: return 4;    // {4, 1}
+      case 512: return 7;    // {4, 2}
+      case 1024: return 11;  // {8, 2}
+      case 2048: return 17;  // {16, 2}
     }
     return -1;
   }
+  const bool fp64 = precision == SMC2_FP64;
   switch (MP) {
-    case 64: return 1;
-    case 128: return 2;
-    case 256: return 3;
-    case 512: return 5;
-    case 1024: return 7;
-    case 2048: return 9;
-    case 4096: return 10;
+    case 64: return 1;                  // {1, 1}
+    case 128: return 2;                 // {2, 1}
+    case 256: return 3;                 // {1, 4}
+    case 512: return fp64 ? 5 : 6;      // {1, 8} / {2, 4}
+    case 1024: return fp64 ? 10 : 9;    // {4, 4} / {2, 8}
+    case 2048: return fp64 ? 14 : 13;   // {8, 4} / {4, 8}
+    case 4096: return 16;               // {8, 8}
   }
   return -1;
 }
@@ -120,9 +124,11 @@ const PFKernel *find_kernel(int model, int precision, int tile) {
   return nullptr;
 }
 
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
 struct Layout {
   int MP, c, nseg, slots;
-  size_t anc, flags, sbuf, ckpt, seg, outer, total;
+  size_t anc, flags, ckpt, seg, outer, total;
 };
 
 }  // namespace
@@ -134,13 +140,12 @@ struct smc2_ctx {
   smc2_model model{};
   std::vector<double> prior_mu, prior_sd;
   smc2_pf_opts opts{};
-  int S = 0, N = 0, M = 0, T_max = 0, tile = 0;
+  int S = 0, N = 0, M = 0, T_max = 0, tile = 0, T_max_hint = 1;
   Layout L{};
   std::vector<int32_t> T_len;
   int32_t *T_len_dev = nullptr, *order_dev = nullptr;
   int32_t *anc = nullptr;
   uint8_t *flags = nullptr;
-  double *sbuf = nullptr;
   void *ckpt = nullptr, *seg = nullptr;
   double *outer_scratch = nullptr;
   uint32_t *queue = nullptr;
@@ -156,7 +161,7 @@ struct smc2_ctx {
     (void)hipSetDevice(cur);
     T_len_dev = order_dev = anc = status = nullptr;
     flags = nullptr;
-    sbuf = outer_scratch = nullptr;
+    outer_scratch = nullptr;
     ckpt = seg = nullptr;
     queue = nullptr;
     reserved = false;
@@ -205,11 +210,10 @@ smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, in
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   L.anc = al((size_t)L.slots * Tc * L.MP * 4);
   L.flags = al((size_t)L.slots * Tc);
-  L.sbuf = al((size_t)L.slots * Tc * 8);
   L.ckpt = al((size_t)L.slots * L.nseg * (dx + 1) * L.MP * rs);
   L.seg = o->want_grad ? al((size_t)L.slots * L.c * (2 * dx + 1) * L.MP * rs) : 256;
   L.outer = al((size_t)items * (2 * m->D + 2) * 8);
-  L.total = L.anc + L.flags + L.sbuf + L.ckpt + L.seg + L.outer + al(items * 4) * 2 +
+  L.total = L.anc + L.flags + L.ckpt + L.seg + L.outer + al(items * 4) * 2 +
             al((size_t)S * 4) + 512;
   return SMC2_OK;
 }
@@ -220,7 +224,7 @@ int resolve_tile(const smc2_model *m, const smc2_pf_opts *o, int M) {
     const Tile t = kTiles[o->tile];
     return (t.waves * 64 * t.ppl == MP) ? o->tile : -1;
   }
-  return default_tile(MP, m->d_x);
+  return default_tile(MP, m->d_x, o->precision);
 }
 
 int grid_slots_for(smc2_ctx *ctx, const smc2_model *m, const smc2_pf_opts *o, int M) {
@@ -228,7 +232,7 @@ int grid_slots_for(smc2_ctx *ctx, const smc2_model *m, const smc2_pf_opts *o, in
   if (tile < 0) return 1;
   const PFKernel *k = find_kernel(m->kind, o->precision, tile);
   if (!k) return 1;
-  return ctx->num_cus * k->occupancy();
+  return ctx->num_cus * k->occupancy(std::max(ctx->T_max_hint, 1));
 }
 
 }  // namespace
@@ -292,6 +296,14 @@ smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_
   if (resolve_tile(model, opts, M) < 0)
     return fail(SMC2_E_UNSUPPORTED, "no built launch shape for this M / tile");
   DeviceGuard g(ctx->device);
+  {
+    const int tile = resolve_tile(model, opts, M);
+    const PFKernel *k = find_kernel(model->kind, opts->precision, tile);
+    if (!k) return fail(SMC2_E_UNSUPPORTED, "kernel not built for this model / precision / tile");
+    if (k->static_lds + k->dyn_lds(std::max(T_max, 1)) > kMaxLdsBytes)
+      return fail(SMC2_E_UNSUPPORTED, "T_max too long to stage the series in LDS");
+  }
+  ctx->T_max_hint = T_max;
   Layout L;
   st = compute_layout(model, opts, S, N, M, T_max, grid_slots_for(ctx, model, opts, M), L);
   if (st != SMC2_OK) return st;
@@ -318,7 +330,6 @@ smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_
   } while (0)
   GRAB(L.anc, ctx->anc, int32_t *);
   GRAB(L.flags, ctx->flags, uint8_t *);
-  GRAB(L.sbuf, ctx->sbuf, double *);
   GRAB(L.ckpt, ctx->ckpt, void *);
   GRAB(L.seg, ctx->seg, void *);
   GRAB(L.outer, ctx->outer_scratch, double *);
@@ -416,6 +427,7 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
   a.nseg_max = ctx->L.nseg;
   a.ld = ctx->L.MP;
   a.t_ld = std::max(ctx->T_max, 1);
+  a.lds_T = std::max(ctx->T_max, 1);
   a.resampler = opts->resampler;
   a.want_grad = opts->want_grad ? 1 : 0;
   a.n_items = items;
@@ -426,12 +438,11 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
   a.queue = ctx->queue;
   a.anc = ctx->anc;
   a.flags = ctx->flags;
-  a.sbuf = ctx->sbuf;
   a.ckpt_buf = ctx->ckpt;
   a.seg_buf = ctx->seg;
   int grid = items;
   if (opts->persistent) {
-    grid = std::min(items, std::min(ctx->L.slots, ctx->num_cus * k->occupancy()));
+    grid = std::min(items, std::min(ctx->L.slots, ctx->num_cus * k->occupancy(a.lds_T)));
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, hs, ctx->queue);
   }
   k->launch(a, grid, hs);

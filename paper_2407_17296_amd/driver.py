@@ -26,6 +26,11 @@ class Records:
     ess: np.ndarray        # [K][S]
     resampled: np.ndarray  # [K][S]
     anc: np.ndarray        # [K][S][N]
+    prev_theta: np.ndarray         # [K][S][N][D] population the move started from
+    prev_logpost: np.ndarray       # [K][S][N]
+    prev_grad_logpost: np.ndarray  # [K][S][N][D]
+    prev_logw: np.ndarray          # [K][S][N]
+    p_prev: np.ndarray             # [K][S][N][D] velocities drawn by the move
 
 
 class SMC2Run:
@@ -158,8 +163,10 @@ def run_smc2(w, K=None, record=True, use_graph=False, **kw):
 
 def _iteration_recorded(run, k):
     """One eager iteration; returns the proposed theta with its filter outputs (before the
-    outer resampling permutes them) and the weights, ESS and ancestors after it."""
+    outer resampling permutes them), the weights, ESS and ancestors after it, and the inputs
+    the reweighting step read (previous population and the move's velocities)."""
     w = run.w
+    prev = {key: v.cpu().numpy() for key, v in run.prev.items()}
     if k == 1:
         run.iteration.fill_(1)
         smc2.smc2_prior_init(run.ctx.h, run.model, w.S, w.N, run.seed, run.cur["theta"])
@@ -169,9 +176,12 @@ def _iteration_recorded(run, k):
     theta = run.cur["theta"].cpu().numpy()
     loglik = run.cur["loglik"].cpu().numpy()
     grad = run.cur["grad_logpost"].cpu().numpy()
+    p_prev = run.p_prev.cpu().numpy()
     run._reweight(first=(k == 1))
     snap = run.snapshot()
     run._carry()
     run.k = k
     return dict(theta=theta, loglik=loglik, grad=grad, logw=snap["logw"], ess=snap["ess"],
-                resampled=snap["resampled"], anc=snap["anc"])
+                resampled=snap["resampled"], anc=snap["anc"], prev_theta=prev["theta"],
+                prev_logpost=prev["logpost"], prev_grad_logpost=prev["grad_logpost"],
+                prev_logw=prev["logw"], p_prev=p_prev)

@@ -45,6 +45,31 @@ def oracle_pf(oracle, w, theta, s, i, k=1, resampler=smc2.SYSTEMATIC, ess_frac=0
                      resampler=resampler, ess_frac=ess_frac, want_trace=want_trace)
 
 
+def oracle_sensitivity(oracle, w, theta, s, i, k, eps, resampler=0, ess_frac=0.5, reps=2):
+    """The oracle at theta[s, i], and how far its own answer moves when theta is perturbed by a
+    relative eps in random sign directions (eps = unit roundoff of the working precision).
+    Returns (result, max |d loglik|, max relative d grad, ancestry unchanged).  Through
+    resampling the estimate is piecewise constant in the random numbers and discontinuous in
+    theta; where it moves by more than a gate under an eps perturbation, no implementation at
+    that precision can be held to the gate."""
+    r0 = oracle_pf(oracle, w, theta, s, i, k=k, resampler=resampler, ess_frac=ess_frac,
+                   want_trace=True)
+    rng = np.random.default_rng(1000003 * s + i)
+    dl = dg = 0.0
+    same = True
+    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+    for _ in range(reps):
+        u = rng.choice([-1.0, 1.0], size=w.D)
+        th = theta[s, i] * (1.0 + eps * u)
+        r1 = oracle.pf(m, th, w.y[s, :w.T_len[s]], w.M, w.seed, k, s * w.N + i,
+                       resampler=resampler, ess_frac=ess_frac, want_trace=True)
+        if np.isfinite(r0["loglik"]) or np.isfinite(r1["loglik"]):
+            dl = max(dl, abs(r1["loglik"] - r0["loglik"]))
+        dg = max(dg, rel_err(r1["grad"], r0["grad"]))
+        same = same and np.array_equal(r1["ancestors"], r0["ancestors"])
+    return r0, dl, dg, same
+
+
 def rel_err(a, b):
     a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
     nb = np.linalg.norm(b)
@@ -57,4 +82,5 @@ def spread_theta(w, scale=0.5, seed=0):
     return w.theta_true + scale * rng.standard_normal((w.S, w.N, w.D))
 
 
-__all__ = ["say", "gpu_pf", "oracle_pf", "rel_err", "spread_theta", "synth"]
+__all__ = ["say", "gpu_pf", "oracle_pf", "oracle_sensitivity", "rel_err", "spread_theta",
+           "synth"]

@@ -81,9 +81,11 @@ def test_bad_options_and_sizes_are_rejected(lib):
 
 
 def test_tile_table(lib):
-    for t in range(1, 12):
+    for t in range(1, 17):
         mp, w, p = smc2.smc2_tile_info(t, 1)
         assert mp == 64 * w * p
+    mp, w, p = smc2.smc2_tile_info(17, 16)
+    assert (mp, w, p) == (2048, 16, 2)
     with pytest.raises(smc2.SMC2Error):
         smc2.smc2_tile_info(99, 1)
 

@@ -14,40 +14,95 @@ def _oracle_run(oracle, w, K, s=0):
     return oracle.smc2_run(m, w.y[s, :w.T_len[s]], w.N, w.M, K, w.gamma, w.seed, series=s)
 
 
+# Priors concentrated where the filters are stable at FP64 resolution: with the configs' N(0, 1)
+# priors a few prior draws have explosive dynamics (|a| > 1.3 for the LG model), whose filter
+# output moves under a one-ulp change of theta, and the weights of one such sample change the
+# ESS and so the whole later trajectory.  The sampler's arithmetic is the same either way.
+PRIORS = {0: ([0.6, 0.0, -0.5], [0.2, 0.5, 0.5]), 3: ([1.0, 0.0], [0.3, 0.3])}
+
+
+def _check_iteration(oracle, w, rec, k, s=0, pf_items=8):
+    """Iteration k (0-based) of a recorded GPU run against the oracle's functions applied to the
+    same inputs the GPU read: the move (k > 0), the filter at the GPU's theta, the prior and
+    L-kernel weights, ESS, the resampling decision and the outer ancestors."""
+    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+    N, D, kk = w.N, w.D, k + 1
+    lib = oracle.lib()
+    th = rec.theta[k, s]
+    if k == 0:
+        z = np.array([[lib.orc_normal(w.seed, 0xFFFFFFFF, s * N + i, oracle.c3(1, oracle.PRIOR_NORMAL), p)
+                       for p in range(D)] for i in range(N)])
+        assert np.allclose(th, w.prior_mu + w.prior_sd * z, rtol=1e-14, atol=1e-14)
+    else:
+        for i in range(N):
+            xi = [lib.orc_normal(w.seed, 0xFFFFFFFF, s * N + i, oracle.c3(kk, oracle.MOVE_NORMAL), p)
+                  for p in range(D)]
+            tn, pp = oracle.langevin_move(w.gamma, rec.prev_theta[k, s, i],
+                                          rec.prev_grad_logpost[k, s, i], xi)
+            assert np.allclose(th[i], tn, rtol=1e-14, atol=1e-14), (k, i)
+            assert np.allclose(rec.p_prev[k, s, i], pp, rtol=1e-14, atol=1e-14), (k, i)
+    for i in range(0, N, max(1, N // pf_items)):
+        r = oracle.pf(m, th[i], w.y[s, :w.T_len[s]], w.M, w.seed, kk, s * N + i)
+        assert rec.loglik[k, s, i] == pytest.approx(r["loglik"], rel=1e-12), (k, i)
+        assert np.linalg.norm(rec.grad[k, s, i] - r["grad"]) <= 1e-9 * np.linalg.norm(r["grad"]), (k, i)
+    logw = np.empty(N)
+    for i in range(N):
+        lp, gp = oracle.log_prior(m, th[i])
+        lpost = lp + rec.loglik[k, s, i]
+        if k == 0:
+            logw[i] = rec.loglik[k, s, i]
+        elif rec.prev_logw[k, s, i] == -np.inf or lpost == -np.inf:
+            logw[i] = -np.inf
+        else:
+            inc = lpost - rec.prev_logpost[k, s, i]
+            inc += oracle.lkernel_log_ratio(w.gamma, rec.prev_grad_logpost[k, s, i],
+                                            rec.grad[k, s, i] + gp, rec.p_prev[k, s, i])
+            logw[i] = rec.prev_logw[k, s, i] + inc
+    mx = logw.max()
+    e = np.exp(logw - mx)
+    ess = e.sum() ** 2 / np.sum(e * e)
+    assert rec.ess[k, s] == pytest.approx(ess, rel=1e-12), k
+    res = ess < N / 2
+    assert bool(rec.resampled[k, s]) == res, k
+    if res:
+        nu = lib.orc_uniform(w.seed, 0xFFFFFFFF, s, oracle.c3(kk, oracle.OUTER_RESAMPLE_UNIFORM), 0)
+        a = oracle.resample_lower_bound(e, (np.arange(N) + nu) / N)
+        assert np.array_equal(rec.anc[k, s], a), k
+        want = mx + np.log(e.sum()) - np.log(N)
+        assert np.allclose(rec.logw[k, s], want, rtol=1e-13, atol=1e-13), k
+    else:
+        assert np.array_equal(rec.anc[k, s], np.arange(N)), k
+        assert np.allclose(rec.logw[k, s], logw, rtol=1e-13, atol=1e-13), k
+    return res
+
+
 @pytest.mark.parametrize("index,kw,K", [(0, {}, 10), (3, dict(N=64, M=128, T=40), 6)])
-def test_fp64_smc2_trajectory_matches_oracle(oracle, index, kw, K):
+def test_fp64_smc2_iterations_match_oracle(oracle, index, kw, K):
+    """Every iteration's move, filter and reweight/resample equal the oracle's on the GPU's own
+    inputs; the whole trajectory stays within rounding drift of the oracle's own run."""
     w = synth.make(index, **kw)
+    w.prior_mu, w.prior_sd = (np.array(v, dtype=float) for v in PRIORS[index])
     say("  smc2 %s N=%d M=%d K=%d" % (w.name, w.N, w.M, K))
     run, rec = driver.run_smc2(w, K=K, precision=smc2.FP64)
     run.close()
+    resampled = [k + 1 for k in range(K) if _check_iteration(oracle, w, rec, k)]
     o = _oracle_run(oracle, w, K)
-    for k in range(K):
-        assert np.allclose(rec.theta[k, 0], o["theta"][k], rtol=0, atol=1e-10), k
-        assert np.allclose(rec.loglik[k, 0], o["loglik"][k], rtol=1e-11, atol=1e-11), k
-        assert np.allclose(rec.grad[k, 0], o["grad"][k], rtol=1e-8, atol=1e-8), k
-        assert rec.ess[k, 0] == pytest.approx(o["ess"][k], rel=1e-10), k
-        assert rec.resampled[k, 0] == o["resampled"][k], k
-        assert np.array_equal(rec.anc[k, 0], o["anc"][k]), k
-        lw = o["logw"][k]
-        if o["resampled"][k]:
-            mx = lw.max()
-            want = mx + np.log(np.sum(np.exp(lw - mx))) - np.log(w.N)
-            assert np.allclose(rec.logw[k, 0], want, rtol=1e-11, atol=1e-10), k
-        else:
-            assert np.allclose(rec.logw[k, 0], lw, rtol=1e-11, atol=1e-10), k
-    say("  %d iterations match; resampled at %s" % (K, list(np.nonzero(o["resampled"])[0] + 1)))
+    drift = max(np.max(np.abs(rec.theta[k, 0] - o["theta"][k])) for k in range(K))
+    assert drift < 1e-6
+    assert list(np.nonzero(o["resampled"])[0] + 1) == resampled
+    say("  %d iterations match step by step; resampled at %s; max theta drift vs the oracle's "
+        "own run %.1e" % (K, resampled, drift))
 
 
 def test_multi_series_outer_step_is_per_series(oracle):
     w = synth.make(4, S=3, N=16, M=64, T=30)
+    w.prior_mu, w.prior_sd = np.array([-1.0, 1.5, -1.4]), np.array([0.3, 0.3, 0.3])
     K = 4
     run, rec = driver.run_smc2(w, K=K, precision=smc2.FP64)
     run.close()
     for s in range(w.S):
-        o = _oracle_run(oracle, w, K, s=s)
         for k in range(K):
-            assert np.allclose(rec.theta[k, s], o["theta"][k], atol=1e-10), (s, k)
-            assert np.array_equal(rec.anc[k, s], o["anc"][k]), (s, k)
+            _check_iteration(oracle, w, rec, k, s=s, pf_items=4)
 
 
 def test_graph_replay_equals_eager():
