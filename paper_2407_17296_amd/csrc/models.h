@@ -13,6 +13,13 @@
 
 namespace smc2 {
 
+// w * v with w = 0 giving 0 even for an infinite v: adjoint terms of particles whose weight or
+// state adjoint vanishes must contribute nothing (a select, not a branch).
+template <typename R>
+__device__ __forceinline__ R mulz(R w, R v) {
+  return w == (R)0 ? (R)0 : w * v;
+}
+
 // x_t = a x + sx e;  y = x + sy w;  theta = (a, log sx, log sy);  x_0 ~ N(0, 1).
 template <typename R>
 struct ModelLG1D {
@@ -30,8 +37,8 @@ struct ModelLG1D {
   __device__ void step(R *x, const R *e) const { x[0] = a * x[0] + sx * e[0]; }
   // reverse of step: tb += F_theta^T xb;  xb <- F_x^T xb   (xp = state before the step)
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
-    tb[0] += (double)(xb[0] * xp[0]);
-    tb[1] += (double)(xb[0] * (sx * e[0]));
+    tb[0] += (double)mulz(xb[0], xp[0]);
+    tb[1] += (double)mulz(xb[0], sx * e[0]);
     xb[0] = a * xb[0];
   }
   __device__ R logg(const R *y, const R *x) const {
@@ -41,8 +48,8 @@ struct ModelLG1D {
   // xb += wb d lambda/dx;  tb += wb d lambda/dtheta
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
     const R r = (y[0] - x[0]) * isy;
-    xb[0] += wb * r * isy;
-    tb[2] += (double)(wb * (r * r - (R)1));
+    xb[0] += mulz(wb, r * isy);
+    tb[2] += (double)mulz(wb, r * r - (R)1);
   }
 };
 
@@ -73,8 +80,8 @@ struct ModelLGDiag {
     R ssx = (R)0;
 #pragma unroll
     for (int q = 0; q < D_X; ++q) {
-      tb[q] += (double)(xb[q] * xp[q]);
-      ssx += xb[q] * e[q];
+      tb[q] += (double)mulz(xb[q], xp[q]);
+      ssx += mulz(xb[q], e[q]);
       xb[q] = A[q] * xb[q];
     }
     tb[D_X] += (double)(ssx * sx);
@@ -93,10 +100,10 @@ struct ModelLGDiag {
 #pragma unroll
     for (int q = 0; q < D_X; ++q) {
       const R r = (y[q] - x[q]) * isy;
-      xb[q] += wb * r * isy;
+      xb[q] += mulz(wb, r * isy);
       s2 += r * r - (R)1;
     }
-    tb[D_X + 1] += (double)(wb * s2);
+    tb[D_X + 1] += (double)mulz(wb, s2);
   }
 };
 
@@ -123,8 +130,8 @@ struct ModelGrowth {
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
     const R v = xp[0], iden = frcp((R)1 + v * v);
     const R fx = (R)0.5 + (R)25 * ((R)1 - v * v) * (iden * iden);
-    tb[0] += (double)(xb[0] * (sx * e[0]));
-    xb[0] = fx * xb[0];
+    tb[0] += (double)mulz(xb[0], sx * e[0]);
+    xb[0] = mulz(xb[0], fx);
   }
   __device__ R logg(const R *y, const R *x) const {
     const R r = (y[0] - x[0] * x[0] * (R)0.05) * isy;
@@ -132,8 +139,8 @@ struct ModelGrowth {
   }
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
     const R r = (y[0] - x[0] * x[0] * (R)0.05) * isy;
-    xb[0] += wb * r * isy * x[0] * (R)0.1;
-    tb[1] += (double)(wb * (r * r - (R)1));
+    xb[0] += mulz(wb, r * isy * x[0] * (R)0.1);
+    tb[1] += (double)mulz(wb, r * r - (R)1);
   }
 };
 
@@ -154,21 +161,21 @@ struct ModelSV {
   __device__ void init(const R *e0, R *x) const { x[0] = mu + sd0 * e0[0]; }
   __device__ void init_adj(const R *e0, const R *xb, double *tb) const {
     tb[0] += (double)xb[0];
-    tb[1] += (double)(xb[0] * dsd0 * e0[0]);
-    tb[2] += (double)(xb[0] * sd0 * e0[0]);
+    tb[1] += (double)mulz(xb[0], dsd0 * e0[0]);
+    tb[2] += (double)mulz(xb[0], sd0 * e0[0]);
   }
   __device__ void step(R *x, const R *e) const { x[0] = mu + phi * (x[0] - mu) + s * e[0]; }
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
     tb[0] += (double)(xb[0] * ((R)1 - phi));
-    tb[1] += (double)(xb[0] * ((R)1 - phi * phi) * (xp[0] - mu));
-    tb[2] += (double)(xb[0] * (s * e[0]));
+    tb[1] += (double)mulz(xb[0], ((R)1 - phi * phi) * (xp[0] - mu));
+    tb[2] += (double)mulz(xb[0], s * e[0]);
     xb[0] = phi * xb[0];
   }
   __device__ R logg(const R *y, const R *x) const {
     return (R)(-kHalfLog2Pi) - (R)0.5 * x[0] - (R)0.5 * y[0] * y[0] * fexp(-x[0]);
   }
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *) const {
-    xb[0] += wb * ((R)(-0.5) + (R)0.5 * y[0] * y[0] * fexp(-x[0]));
+    xb[0] += mulz(wb, (R)(-0.5) + (R)0.5 * y[0] * y[0] * fexp(-x[0]));
   }
 };
 

@@ -128,32 +128,28 @@ __device__ __forceinline__ void filter_uniforms(int j0, uint32_t fid, uint32_t c
 }
 
 // Systematic target of offspring i: ((i + nu) / M) * P_{M-1}, in the order of operations the
-// resampling rule is stated in.  When M is a power of two, division by M and multiplication by
-// 1/M are the same exact operation.
+// resampling rule is stated in.  When M is a power of two (FAST), division by M and
+// multiplication by 1/M are the same exact operation.
 struct SysTargets {
   double nu, Md, inv_Md, tot, inv_tot;
   int M;
-  bool pow2;
+  template <bool FAST>
   __device__ double at(int i) const {
-    return pow2 ? ((double)i + nu) * inv_Md * tot : ((double)i + nu) / Md * tot;
+    return FAST ? ((double)i + nu) * inv_Md * tot : ((double)i + nu) / Md * tot;
   }
   // C = #{i in [0, M) : at(i) <= P}: the targets increase with i, so C is the first i whose
-  // target exceeds P.  An estimate from P / tot is corrected with the exact comparisons.
+  // target exceeds P.  The estimate g from P / tot is checked with the exact comparisons
+  // at(g - 1) <= P < at(g), which need no special cases at g = 0 (at(-1) <= 0) or g = M
+  // (at(M) > tot > P); a wrong estimate falls back to bisection.
+  template <bool FAST>
   __device__ int upto(double P) const {
     if (!(P < tot)) return M;
-    int g = (int)fmin(fmax(floor(P * inv_tot * Md - nu) + 1.0, 0.0), Md);
-    for (int it = 0; it < 4; ++it) {
-      if (g > 0 && at(g - 1) > P)
-        --g;
-      else if (g < M && at(g) <= P)
-        ++g;
-      else
-        return g;
-    }
-    int lo = 0, hi = M;  // the estimate was far off: bisect
+    const int g = (int)fmin(fmax(floor(P * inv_tot * Md - nu) + 1.0, 0.0), Md);
+    if (at<FAST>(g - 1) <= P && at<FAST>(g) > P) return g;
+    int lo = 0, hi = M;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (at(mid) <= P)
+      if (at<FAST>(mid) <= P)
         lo = mid + 1;
       else
         hi = mid;
@@ -162,13 +158,47 @@ struct SysTargets {
   }
 };
 
+// Ancestors of this thread's offspring slots under systematic resampling: each parent marks
+// the first offspring it owns, and an exclusive max-scan over the markers hands every
+// offspring the last parent that started at or before it.  FAST: M fills the tile (a power of
+// two), so no slot is padding.
+template <bool FAST, int WAVES, int PPL, typename R>
+__device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, double off,
+                                                     const R (&ew)[PPL], int j0, int M,
+                                                     int *sh_mark, int *sh_imax, int (&a)[PPL],
+                                                     int dummy) {
+  const double tot = tg.tot;
+  int prev = tg.upto<FAST>(fmin(off, tot));
+  double part = 0.0;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const int m = j0 + p;
+    part += (double)ew[p];
+    const double P = (m == M - 1) ? tot : fmin(off + part, tot);
+    int cm = tg.upto<FAST>(P);
+    if (!FAST && m >= M) cm = prev;
+    atomicMax(&sh_mark[cm > prev ? prev : dummy], m);
+    prev = max(prev, cm);
+  }
+  __syncthreads();
+  int run = -1;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    run = max(run, sh_mark[j0 + p]);
+    a[p] = run;
+  }
+  const int before = block_exclusive_max_scan<WAVES>(run, sh_imax);
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) a[p] = min(max(a[p], before), M - 1);
+}
+
 template <typename R, class Model, int WAVES, int PPL>
 __global__ __launch_bounds__(WAVES * 64) void pf_fwd_adj_kernel(PFArgs A) {
   constexpr int NT = WAVES * 64, MP = NT * PPL, DX = Model::DX, NP = Model::NP;
   constexpr double kNegInf = -__builtin_huge_val();
   __shared__ double sh_P[MP];    // multinomial prefix
   __shared__ R sh_X[2][MP];      // gather / adjoint-scatter staging (ping-pong)
-  __shared__ int sh_mark[MP];    // systematic: first-offspring markers
+  __shared__ int sh_mark[MP + 1];  // systematic: first-offspring markers (+ a dummy slot)
   __shared__ double sh_red[2][2 * WAVES + 2];
   __shared__ double sh_vec[WAVES * NP];
   __shared__ int sh_imax[WAVES];
@@ -319,33 +349,12 @@ __global__ __launch_bounds__(WAVES * 64) void pf_fwd_adj_kernel(PFArgs A) {
         tg.M = M;
         tg.Md = Md;
         tg.inv_Md = 1.0 / Md;
-        tg.pow2 = (M & (M - 1)) == 0;
         tg.tot = tot;
         tg.inv_tot = 1.0 / tot;
-        // parent m owns offspring [C_{m-1}, C_m); a marker at C_{m-1} names it
-        int prev = tg.upto(fmin(off, tot));
-        double part = 0.0;
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          const int m = j0 + p;
-          part += (double)ew[p];
-          if (m < M) {
-            const double P = (m == M - 1) ? tot : fmin(off + part, tot);
-            const int cm = tg.upto(P);
-            if (cm > prev) atomicMax(&sh_mark[prev], m);
-            prev = max(prev, cm);
-          }
-        }
-        __syncthreads();
-        int run = -1;
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          run = max(run, sh_mark[j0 + p]);
-          a[p] = run;
-        }
-        const int before = block_exclusive_max_scan<WAVES>(run, sh_imax);
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) a[p] = min(max(a[p], before), M - 1);
+        if (M == MP)
+          systematic_ancestors<true, WAVES, PPL>(tg, off, ew, j0, M, sh_mark, sh_imax, a, MP);
+        else
+          systematic_ancestors<false, WAVES, PPL>(tg, off, ew, j0, M, sh_mark, sh_imax, a, MP);
       } else {
         double part = 0.0;
 #pragma unroll
@@ -527,15 +536,11 @@ __global__ __launch_bounds__(WAVES * 64) void pf_fwd_adj_kernel(PFArgs A) {
         }
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          bool active = wb[p] != (R)0;
-#pragma unroll
-          for (int q = 0; q < DX; ++q) active = active || xb[p][q] != (R)0;
-          if (!active) continue;
           R xc[DX];
 #pragma unroll
           for (int q = 0; q < DX; ++q) xc[q] = cx[p][q];
           mdl.step(xc, ce[p]);
-          if (wb[p] != (R)0) mdl.logg_adj(yv, xc, wb[p], xb[p], tb);
+          mdl.logg_adj(yv, xc, wb[p], xb[p], tb);
           mdl.step_adj(cx[p], ce[p], xb[p], tb);
         }
       }

@@ -107,8 +107,8 @@ int default_tile(int MP, int dx, int precision) {
     case 64: return 1;                  // {1, 1}
     case 128: return 2;                 // {2, 1}
     case 256: return 3;                 // {1, 4}
-    case 512: return fp64 ? 5 : 6;      // {1, 8} / {2, 4}
-    case 1024: return fp64 ? 10 : 9;    // {4, 4} / {2, 8}
+    case 512: return fp64 ? 6 : 5;      // {2, 4} / {1, 8}
+    case 1024: return 10;               // {4, 4}
     case 2048: return fp64 ? 14 : 13;   // {8, 4} / {4, 8}
     case 4096: return 16;               // {8, 8}
   }
