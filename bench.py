@@ -28,25 +28,25 @@ sys.path.insert(0, ROOT)
 # packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-slots/s
 # (the FP32 vector rate without packed math, 78.6 TFLOP/s counting an FMA as two).
 PEAK_HBM_GBS = 8000.0
-PEAK_VALU_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+PEAK_VALU_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12  # T wave-lane instructions per second
 
-# Algorithmic VALU lane-slots per particle-step of the fused forward+adjoint for d = 1, counted
-# from the method's arithmetic (not from the executed code): the forward pass, its recompute
-# inside the adjoint and the adjoint sweep each need the step's normal (a quarter of a
-# Philox4x32-10 call, 10 rounds x 6 integer ops, and half a Box-Muller pair: log, sqrt, sin/cos
-# at the quarter-rate transcendental cost of 4 slots), the transition and log g (about 8), and
-# the weight exponential (4); the forward adds the max / sum / ESS reductions (6 per particle,
-# amortised) and the resampling search (log2 M compares for the resampled fraction r); the
-# adjoint adds about 12 for the transposed derivatives.  See the design doc for the itemisation.
+# Algorithmic VALU work per particle-step of the fused forward+adjoint for d = 1, in wave-lane
+# instructions of a direct implementation of the method's arithmetic (itemised in the design doc):
+#   noise      Philox4x32-10 serves 4 particles (10 rounds x 4 instructions / 4 = 10) and half
+#              a Box-Muller pair (11 instructions / 2 = 5.5)                        -> 15.5
+#   model      transition 2, log g 4, weight update and guard 3                      ->  9
+#   normalise  max 1, exp 3, FP64 sums 3, normalised log-weight 1                     ->  8
+#   resample   per resampled step: prefix 1, offspring count 8 + two exact targets 8
+#              + compares 2, marker / max-scan 2, gather 1                           -> 22 r
+# The forward needs all four; the recompute inside the adjoint needs noise, model, the weight
+# exponential at resampled steps (3 r) and the stored-ancestor gather (1 r); the reverse sweep
+# needs the transition again (2), the transposed derivatives (11) and the scatter (2 r).
 def alg_slots_per_particle_step(M, r):
-    philox = 0.25 * 10 * 6
-    box_muller = 0.5 * (4 * 4 + 6)
-    model = 8 + 4
-    per_pass = philox + box_muller + model
-    forward = per_pass + 6 + r * (np.log2(M) + 4)
-    recompute = per_pass + r * 2
-    adjoint = 12
-    return forward + recompute + adjoint
+    noise, model, normalise = 15.5, 9.0, 8.0
+    forward = noise + model + normalise + 22.0 * r
+    recompute = noise + model + 4.0 * r
+    reverse = 13.0 + 2.0 * r
+    return forward + recompute + reverse
 
 
 def algorithmic_bytes_per_particle_step(r, c, rs, d=1):
@@ -133,17 +133,46 @@ def cpu_baseline(w, seconds, threads):
                        "%.1f s wall" % (i, w.M, int(w.T_len[0]), w.name, dt))
 
 
-def measure(w, precision, steps, warmup, with_kernel=True):
-    from paper_2407_17296_amd import driver
-    run = driver.SMC2Run(w, precision=precision)
+def measure(w, precision, steps, warmup, with_kernel=True, tune=True):
+    from paper_2407_17296_amd import autotune, driver
+    t = autotune.tune(w, precision) if tune else dict(tile=0, ckpt=0)
+    run = driver.SMC2Run(w, precision=precision, tile=t["tile"], ckpt_interval=t["ckpt"])
     gpu_s, wall = _timed_graph(run, steps, warmup)
     out = dict(seconds=gpu_s, wall=wall, ms_per_step=1e3 * gpu_s / steps,
-               value=w.particle_steps() * steps / gpu_s)
+               value=w.particle_steps() * steps / gpu_s, tile=t["tile"], ckpt=t["ckpt"])
     if with_kernel:
         out["kernel_s"] = _kernel_duration(run, max(3, min(10, steps)))
         out["resample_fraction"] = _resample_fraction(run)
     run.close()
     return out
+
+
+def kernel_sources_sha():
+    """Hash of the sources of the fused filter kernel (counters recorded for another version
+    of the kernel no longer describe it)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2407_17296_amd", "csrc")
+    for f in ("device_common.h", "models.h", "pf_kernel.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload_name, tile, precision):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the current
+    kernel sources with the same workload, launch shape and precision; else None."""
+    path = os.path.join(ROOT, "profiles", "pf_fwd_adj_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for r in rec.get("records", []):
+        if (r.get("kernel_sha") == kernel_sources_sha() and r.get("workload") == workload_name
+                and r.get("tile") == tile and r.get("precision") == precision):
+            return r.get("hbm_bytes_per_launch")
+    return None
 
 
 def main():
@@ -156,6 +185,11 @@ def main():
     ap.add_argument("--no-growth", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="finish with a plain device copy of this many MiB (a known-size "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's default launch shapes instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the hot path shards by parameter sample and this build "
@@ -168,38 +202,47 @@ def main():
     w = synth.make(args.config)
     print("[bench] workload %s S=%d N=%d M=%d T=%d, %d warmup + %d timed iterations" % (
         w.name, w.S, w.N, w.M, w.T_max, args.warmup, args.steps), file=sys.stderr, flush=True)
-    mixed = measure(w, smc2.MIXED, args.steps, args.warmup)
+    tune = not args.no_tune
+    mixed = measure(w, smc2.MIXED, args.steps, args.warmup, tune=tune)
     print("[bench] mixed: %.3f ms/iteration" % mixed["ms_per_step"], file=sys.stderr, flush=True)
 
     res = {}
     if not args.no_fp64:
-        fp64 = measure(w, smc2.FP64, max(3, args.steps // 2), 1, with_kernel=False)
-        res["fp64_plain"] = dict(value=fp64["value"], ms_per_step=fp64["ms_per_step"])
+        fp64 = measure(w, smc2.FP64, max(3, args.steps // 2), 1, with_kernel=False, tune=tune)
+        res["fp64_plain"] = dict(value=fp64["value"], ms_per_step=fp64["ms_per_step"],
+                                 tile=fp64["tile"], ckpt=fp64["ckpt"])
         res["mixed_over_fp64"] = mixed["value"] / fp64["value"]
         print("[bench] fp64: %.3f ms/iteration" % fp64["ms_per_step"], file=sys.stderr, flush=True)
     if not args.no_growth:
         wg = synth.make(3)
-        gm = measure(wg, smc2.MIXED, 5, 1, with_kernel=False)
-        gf = measure(wg, smc2.FP64, 3, 1, with_kernel=False)
+        gm = measure(wg, smc2.MIXED, 5, 1, with_kernel=False, tune=tune)
+        gf = measure(wg, smc2.FP64, 3, 1, with_kernel=False, tune=tune)
         res["growth_workload"] = dict(workload="%s T=%d N=%d M=%d" % (wg.name, wg.T_max, wg.N, wg.M),
                                       mixed_value=gm["value"], fp64_value=gf["value"],
-                                      mixed_over_fp64=gm["value"] / gf["value"])
+                                      mixed_over_fp64=gm["value"] / gf["value"],
+                                      mixed_tile=gm["tile"], fp64_tile=gf["tile"])
         print("[bench] growth mixed %.3f ms, fp64 %.3f ms" % (gm["ms_per_step"], gf["ms_per_step"]),
               file=sys.stderr, flush=True)
 
+    from paper_2407_17296_amd import smc2 as _smc2
     ps_launch = w.particle_steps()
     r = mixed["resample_fraction"]
-    c = int(np.ceil(np.sqrt(w.T_max)))
+    c = mixed["ckpt"] or int(np.ceil(np.sqrt(w.T_max)))
+    _, waves, ppl = _smc2.smc2_tile_info(mixed["tile"], w.d) if mixed["tile"] else (0, 0, 0)
     slots = alg_slots_per_particle_step(w.M, r)
     achieved = slots * ps_launch / mixed["kernel_s"] / 1e12
     hbm_bytes = algorithmic_bytes_per_particle_step(r, c, 4) * ps_launch
+    traffic = recorded_traffic(w.name, mixed["tile"], 1)
     roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TSLOTS, unit="Tslot/s",
-                frac=achieved / PEAK_VALU_TSLOTS, traffic=None,
-                kernel="pf_fwd_adj_kernel<float, ModelLG1D<float>, 4, 4>",
+                frac=achieved / PEAK_VALU_TSLOTS, traffic=traffic,
+                kernel="pf_fwd_adj_kernel<float, ModelLG1D<float>, %d, %d>" % (waves, ppl),
+                tile=mixed["tile"], ckpt_interval=c,
                 kernel_ms=1e3 * mixed["kernel_s"], alg_slots_per_particle_step=slots,
                 resample_fraction=r,
+                hbm_algorithmic_bytes_per_launch=hbm_bytes,
                 hbm_algorithmic_GBs=hbm_bytes / mixed["kernel_s"] / 1e9,
-                hbm_frac=hbm_bytes / mixed["kernel_s"] / 1e9 / PEAK_HBM_GBS)
+                hbm_frac=hbm_bytes / mixed["kernel_s"] / 1e9 / PEAK_HBM_GBS,
+                kernel_sources_sha=kernel_sources_sha())
 
     cpu = None
     if not args.no_cpu:
@@ -229,6 +272,13 @@ def main():
         "cpu_baseline": cpu,
     }
     line.update(res)
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib * 262144, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = src.numel() * 4
     print(json.dumps(line))
 
 

@@ -1,0 +1,116 @@
+"""Autotuner of the fused filter's launch shape and checkpoint interval.
+
+For a workload it times every built launch shape whose capacity fits the particle count
+(waves per workgroup x 64 x particles per lane = the next power of two >= M) and a few
+checkpoint intervals, each for a handful of launches timed with HIP events on the launch
+stream, and keeps the fastest.  Results are cached in a JSON file keyed by model, state and
+parameter dimension, particle count, series-length and item-count buckets, precision and device
+name, so a later run on the same device reuses them.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import smc2
+
+CACHE = os.environ.get("SMC2_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "smc2_autotune.json"))
+NUM_TILES = 18  # indices 1.. of the library's launch-shape table
+CKPT_CANDIDATES = (0, 8, 4)
+
+
+def _bucket(v):
+    p = 1
+    while p < v:
+        p <<= 1
+    return p
+
+
+def key(w, precision, device_name):
+    return "|".join(str(v) for v in (w.kind, w.d, w.D, w.M, _bucket(w.T_max), _bucket(w.S * w.N),
+                                      precision, device_name))
+
+
+def candidate_tiles(w):
+    mp = _bucket(max(w.M, 64))
+    out = []
+    for t in range(1, NUM_TILES):
+        try:
+            cap, _, _ = smc2.smc2_tile_info(t, w.d)
+        except smc2.SMC2Error:
+            continue
+        if cap == mp:
+            out.append(t)
+    return out
+
+
+def time_config(w, precision, tile, ckpt, reps=3, seed_theta=0):
+    """Mean duration (s) of the fused forward+adjoint over `reps` launches."""
+    dev = torch.device("cuda:0")
+    model = smc2.Model.from_workload(w)
+    opts = smc2.pf_opts(precision=precision, tile=tile, ckpt_interval=ckpt)
+    ctx = smc2.Context(model, opts, w.S, w.N, w.M, w.T_len, w.T_max)
+    try:
+        rng = np.random.default_rng(seed_theta)
+        th = torch.tensor(w.theta_true + 0.1 * rng.standard_normal((w.S, w.N, w.D)),
+                          dtype=torch.float64, device=dev)
+        y = torch.tensor(w.y, dtype=torch.float64, device=dev)
+        it = torch.tensor([2], dtype=torch.int32, device=dev)
+        ll = torch.empty((w.S, w.N), dtype=torch.float64, device=dev)
+        g = torch.empty((w.S, w.N, w.D), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream()
+        ctx.pf(th, y, w.seed, it, ll, g, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ctx.pf(th, y, w.seed, it, ll, g, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3 / reps
+    finally:
+        ctx.close()
+
+
+def tune(w, precision, reps=3, use_cache=True, verbose=False):
+    """Best (tile, ckpt) for workload w at `precision`; returns a dict with the timings."""
+    name = torch.cuda.get_device_name(0)
+    k = key(w, precision, name)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        try:
+            with open(CACHE) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        if k in cache:
+            return cache[k]
+    trials = []
+    t0 = time.perf_counter()
+    for tile in candidate_tiles(w):
+        for ckpt in CKPT_CANDIDATES:
+            try:
+                s = time_config(w, precision, tile, ckpt, reps=reps)
+            except smc2.SMC2Error:
+                continue
+            trials.append((s, tile, ckpt))
+            if verbose:
+                print("[autotune] %s prec=%d tile=%d ckpt=%d: %.3f ms" % (w.name, precision, tile,
+                                                                        ckpt, 1e3 * s), flush=True)
+    if not trials:
+        raise RuntimeError("no launch shape could run workload %s" % w.name)
+    s, tile, ckpt = min(trials)
+    res = dict(tile=int(tile), ckpt=int(ckpt), seconds=float(s), trials=len(trials),
+               tuning_seconds=time.perf_counter() - t0,
+               all=[dict(tile=int(t), ckpt=int(c), ms=1e3 * v) for v, t, c in sorted(trials)])
+    if use_cache:
+        cache[k] = res
+        try:
+            os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+            with open(CACHE, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return res
