@@ -111,20 +111,85 @@ __device__ __forceinline__ double uniform_m(uint32_t c0, uint32_t c2, uint32_t c
 }
 
 // ---- wave and workgroup reductions ------------------------------------------------------------
-// Butterfly (xor) reductions: every lane combines the same two operands in the same order at
-// each stage (addition is commutative), so all 64 lanes end with bit-identical results.  The
+// Cross-lane moves use the data-parallel (DPP) modifiers of GFX9 VALU instructions instead of
+// LDS permutes: quad swaps and row mirrors for butterflies inside each row of 16 lanes, row
+// shifts and row broadcasts for scans.  Butterflies combine the same two operands in every lane
+// (addition is commutative), so each row ends with bit-identical values; the four row results
+// are then read as scalars and combined in a fixed order, so the wave result is uniform.  The
 // cross-wave stage reads the per-wave values in wave order, so the workgroup result is also
-// identical in every thread, which keeps data-dependent branches uniform.
+// identical in every thread, which keeps data-dependent branches uniform.  Every lane of the
+// wave must be active.
+enum : int {
+  kDppQuadXor1 = 0xB1,       // quad_perm [1,0,3,2]
+  kDppQuadXor2 = 0x4E,       // quad_perm [2,3,0,1]
+  kDppRowShr1 = 0x111,       // row_shr:n = 0x110 + n (lanes below n in a row keep `old`)
+  kDppRowShr2 = 0x112,
+  kDppRowShr4 = 0x114,
+  kDppRowShr8 = 0x118,
+  kDppRowMirror = 0x140,     // lane 15 - i of the row
+  kDppRowHalfMirror = 0x141, // lane 7 - i of the half row
+  kDppRowBcast15 = 0x142,    // lane 15 of each row to the next row
+  kDppRowBcast31 = 0x143,    // lane 31 to rows 2 and 3
+  kDppWaveShr1 = 0x138       // lane i - 1 of the wave (lane 0 keeps `old`)
+};
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int dpp_i32(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+  const uint64_t o = (uint64_t)__double_as_longlong(old), x = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)dpp_i32<CTRL, ROW_MASK>((int)(uint32_t)o, (int)(uint32_t)x);
+  const uint32_t hi =
+      (uint32_t)dpp_i32<CTRL, ROW_MASK>((int)(uint32_t)(o >> 32), (int)(uint32_t)(x >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t x = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_f64<kDppQuadXor1>(v, v));
+  v = fmax(v, dpp_f64<kDppQuadXor2>(v, v));
+  v = fmax(v, dpp_f64<kDppRowHalfMirror>(v, v));
+  v = fmax(v, dpp_f64<kDppRowMirror>(v, v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += dpp_f64<kDppQuadXor1>(0.0, v);
+  v += dpp_f64<kDppQuadXor2>(0.0, v);
+  v += dpp_f64<kDppRowHalfMirror>(0.0, v);
+  v += dpp_f64<kDppRowMirror>(0.0, v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (lane order).
+__device__ __forceinline__ double wave_inclusive_sum(double v) {
+  v += dpp_f64<kDppRowShr1>(0.0, v);
+  v += dpp_f64<kDppRowShr2>(0.0, v);
+  v += dpp_f64<kDppRowShr4>(0.0, v);
+  v += dpp_f64<kDppRowShr8>(0.0, v);
+  v += dpp_f64<kDppRowBcast15, 0xA>(0.0, v);
+  v += dpp_f64<kDppRowBcast31, 0xC>(0.0, v);
+  return v;
+}
+
+// Inclusive prefix maximum over the 64 lanes of a wave (lane order); values are >= -1.
+__device__ __forceinline__ int wave_inclusive_max(int v) {
+  v = max(v, dpp_i32<kDppRowShr1>(-1, v));
+  v = max(v, dpp_i32<kDppRowShr2>(-1, v));
+  v = max(v, dpp_i32<kDppRowShr4>(-1, v));
+  v = max(v, dpp_i32<kDppRowShr8>(-1, v));
+  v = max(v, dpp_i32<kDppRowBcast15, 0xA>(-1, v));
+  v = max(v, dpp_i32<kDppRowBcast31, 0xC>(-1, v));
   return v;
 }
 
@@ -189,19 +254,14 @@ __device__ __forceinline__ void block_sum_vec(double *v, double *red) {
 template <int WAVES>
 __device__ __forceinline__ double block_exclusive_scan(double v, double *wsum, double &total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double inc = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double n = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += n;
-  }
-  double exc = __shfl_up(inc, 1, 64);
-  if (lane == 0) exc = 0.0;
+  const double inc = wave_inclusive_sum(v);
+  const double exc = dpp_f64<kDppWaveShr1>(0.0, inc);
+  const double wtot = readlane_f64(inc, 63);
   if constexpr (WAVES == 1) {
-    total = __shfl(inc, 63, 64);
+    total = wtot;
     return exc;
   } else {
-    if (lane == 63) wsum[wid] = inc;
+    if (lane == 0) wsum[wid] = wtot;
     __syncthreads();
     double off = 0.0, tot = 0.0;
 #pragma unroll
@@ -215,20 +275,15 @@ __device__ __forceinline__ double block_exclusive_scan(double v, double *wsum, d
   }
 }
 
-// Exclusive max-scan over the workgroup of one int per thread (thread order); -1 for thread 0.
+// Exclusive max-scan over the workgroup of one int (>= -1) per thread (thread order); -1 for
+// thread 0.
 template <int WAVES>
 __device__ __forceinline__ int block_exclusive_max_scan(int v, int *wmax) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int inc = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int n = __shfl_up(inc, o, 64);
-    if (lane >= o) inc = max(inc, n);
-  }
-  int exc = __shfl_up(inc, 1, 64);
-  if (lane == 0) exc = -1;
+  const int inc = wave_inclusive_max(v);
+  int exc = dpp_i32<kDppWaveShr1>(-1, inc);
   if constexpr (WAVES > 1) {
-    if (lane == 63) wmax[wid] = inc;
+    if (lane == 0) wmax[wid] = __builtin_amdgcn_readlane(inc, 63);
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < WAVES; ++w)

@@ -193,7 +193,7 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
 }
 
 template <typename R, class Model, int WAVES, int PPL>
-__global__ __launch_bounds__(WAVES * 64) void pf_fwd_adj_kernel(PFArgs A) {
+__global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <= 4) ? 4 : 1) void pf_fwd_adj_kernel(PFArgs A) {
   constexpr int NT = WAVES * 64, MP = NT * PPL, DX = Model::DX, NP = Model::NP;
   constexpr double kNegInf = -__builtin_huge_val();
   __shared__ double sh_P[MP];    // multinomial prefix
