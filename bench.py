@@ -30,23 +30,26 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12  # T wave-lane instructions per second
 
-# Algorithmic VALU work per particle-step of the fused forward+adjoint for d = 1, in wave-lane
-# instructions of a direct implementation of the method's arithmetic (itemised in the design doc):
-#   noise      Philox4x32-10 serves 4 particles (10 rounds x 4 instructions / 4 = 10) and half
-#              a Box-Muller pair (11 instructions / 2 = 5.5)                        -> 15.5
-#   model      transition 2, log g 4, weight update and guard 3                      ->  9
-#   normalise  max 1, exp 3, FP64 sums 3, normalised log-weight 1                     ->  8
-#   resample   per resampled step: prefix 1, offspring count 8 + two exact targets 8
-#              + compares 2, marker / max-scan 2, gather 1                           -> 22 r
-# The forward needs all four; the recompute inside the adjoint needs noise, model, the weight
-# exponential at resampled steps (3 r) and the stored-ancestor gather (1 r); the reverse sweep
-# needs the transition again (2), the transposed derivatives (11) and the scatter (2 r).
+# Algorithmic VALU work per particle-step of the CRN-PF forward sweep and its adjoint for d = 1,
+# in issue slots of a direct implementation of the method's arithmetic (itemised in the design doc).
+# Full-rate instructions take one slot per lane; quarter-rate ones (the 32 x 32 -> 64-bit
+# integer multiply-add and the transcendental unit: log, sqrt, sin, cos, exp) take four.
+#   noise      a Philox4x32-10 block serves 4 particles: 10 rounds x (2 multiply-adds x 4
+#              + 4 xors) / 4 = 30; half a Box-Muller pair: (9 full + 4 transcendental x 4)
+#              / 2 = 12.5                                                         -> 42.5
+#   model      transition 2, log g 4, weight update and guard 3                   ->  9
+#   normalise  subtract and scale 2, exp 4, FP64 conversion and sums 3, normalised
+#              log-weight 1                                                       -> 10
+#   resample   per resampled step: FP64 prefix 2, offspring count 8 + two exact targets
+#              8 + compares 2, marker / max-scan 1, gather 1                       -> 22 r
+#   adjoint    transposed derivatives of log g and of the transition 13, scatter-add to
+#              the parent at a resampled step 2                                  -> 13 + 2 r
+# Rebuilding the step in the adjoint (from checkpoints) is implementation work, not counted.
 def alg_slots_per_particle_step(M, r):
-    noise, model, normalise = 15.5, 9.0, 8.0
+    noise, model, normalise = 42.5, 9.0, 10.0
     forward = noise + model + normalise + 22.0 * r
-    recompute = noise + model + 4.0 * r
-    reverse = 13.0 + 2.0 * r
-    return forward + recompute + reverse
+    adjoint = 13.0 + 2.0 * r
+    return forward + adjoint
 
 
 def algorithmic_bytes_per_particle_step(r, c, rs, d=1):
@@ -54,6 +57,20 @@ def algorithmic_bytes_per_particle_step(r, c, rs, d=1):
     forward and read in the adjoint at a resampled step (fraction r), and the (x, log W)
     checkpoint written and read once every c steps (rs bytes per value)."""
     return r * 8.0 + 2.0 * (d + 1) * rs / c
+
+
+def design_bytes_per_particle_step(r, c, rs, store_noise, d=1):
+    """HBM bytes the chosen configuration moves by construction: ancestors and checkpoints as
+    above, the stored noise (written once, read once), and for c > 1 the segment rows (state
+    before the step, the noise when not stored, and the weight at resampled steps) written by
+    the recomputation and read by the reverse sweep, plus the ancestors read again there."""
+    b = algorithmic_bytes_per_particle_step(r, c, rs, d)
+    if store_noise:
+        b += 2.0 * d * rs * (1.0 if c == 1 else 1.5)
+    if c > 1:
+        rows = d + (0 if store_noise else d)
+        b += 2.0 * (rows + r) * rs + 4.0 * r
+    return b
 
 
 def _timed_graph(run, steps, warmup):
@@ -135,11 +152,13 @@ def cpu_baseline(w, seconds, threads):
 
 def measure(w, precision, steps, warmup, with_kernel=True, tune=True):
     from paper_2407_17296_amd import autotune, driver
-    t = autotune.tune(w, precision) if tune else dict(tile=0, ckpt=0)
-    run = driver.SMC2Run(w, precision=precision, tile=t["tile"], ckpt_interval=t["ckpt"])
+    t = autotune.tune(w, precision) if tune else dict(tile=0, ckpt=0, store_noise=1)
+    run = driver.SMC2Run(w, precision=precision, tile=t["tile"], ckpt_interval=t["ckpt"],
+                         store_noise=t.get("store_noise", 1))
     gpu_s, wall = _timed_graph(run, steps, warmup)
     out = dict(seconds=gpu_s, wall=wall, ms_per_step=1e3 * gpu_s / steps,
-               value=w.particle_steps() * steps / gpu_s, tile=t["tile"], ckpt=t["ckpt"])
+               value=w.particle_steps() * steps / gpu_s, tile=t["tile"], ckpt=t["ckpt"],
+               store_noise=t.get("store_noise", 1))
     if with_kernel:
         out["kernel_s"] = _kernel_duration(run, max(3, min(10, steps)))
         out["resample_fraction"] = _resample_fraction(run)
@@ -159,9 +178,10 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload_name, tile, precision):
+def recorded_traffic(workload_name, tile, precision, ckpt, store_noise):
     """HBM bytes per launch from the committed counter summary, if it was taken on the current
-    kernel sources with the same workload, launch shape and precision; else None."""
+    kernel sources with the same workload, launch shape, precision, checkpoint interval and
+    noise storage; else None."""
     path = os.path.join(ROOT, "profiles", "pf_fwd_adj_traffic.json")
     try:
         with open(path) as f:
@@ -170,7 +190,8 @@ def recorded_traffic(workload_name, tile, precision):
         return None
     for r in rec.get("records", []):
         if (r.get("kernel_sha") == kernel_sources_sha() and r.get("workload") == workload_name
-                and r.get("tile") == tile and r.get("precision") == precision):
+                and r.get("tile") == tile and r.get("precision") == precision
+                and r.get("ckpt") == ckpt and r.get("store_noise") == store_noise):
             return r.get("hbm_bytes_per_launch")
     return None
 
@@ -210,7 +231,8 @@ def main():
     if not args.no_fp64:
         fp64 = measure(w, smc2.FP64, max(3, args.steps // 2), 1, with_kernel=False, tune=tune)
         res["fp64_plain"] = dict(value=fp64["value"], ms_per_step=fp64["ms_per_step"],
-                                 tile=fp64["tile"], ckpt=fp64["ckpt"])
+                                 tile=fp64["tile"], ckpt=fp64["ckpt"],
+                                 store_noise=fp64["store_noise"])
         res["mixed_over_fp64"] = mixed["value"] / fp64["value"]
         print("[bench] fp64: %.3f ms/iteration" % fp64["ms_per_step"], file=sys.stderr, flush=True)
     if not args.no_growth:
@@ -227,21 +249,26 @@ def main():
     from paper_2407_17296_amd import smc2 as _smc2
     ps_launch = w.particle_steps()
     r = mixed["resample_fraction"]
-    c = mixed["ckpt"] or int(np.ceil(np.sqrt(w.T_max)))
+    c_sqrt = int(np.ceil(np.sqrt(w.T_max)))
+    c = mixed["ckpt"] or c_sqrt
     _, waves, ppl = _smc2.smc2_tile_info(mixed["tile"], w.d) if mixed["tile"] else (0, 0, 0)
     slots = alg_slots_per_particle_step(w.M, r)
     achieved = slots * ps_launch / mixed["kernel_s"] / 1e12
-    hbm_bytes = algorithmic_bytes_per_particle_step(r, c, 4) * ps_launch
-    traffic = recorded_traffic(w.name, mixed["tile"], 1)
+    hbm_bytes = algorithmic_bytes_per_particle_step(r, c_sqrt, 4) * ps_launch
+    design_bytes = design_bytes_per_particle_step(r, c, 4, mixed["store_noise"]) * ps_launch
+    traffic = recorded_traffic(w.name, mixed["tile"], 1, c, mixed["store_noise"])
     roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TSLOTS, unit="Tslot/s",
                 frac=achieved / PEAK_VALU_TSLOTS, traffic=traffic,
                 kernel="pf_fwd_adj_kernel<float, ModelLG1D<float>, %d, %d>" % (waves, ppl),
-                tile=mixed["tile"], ckpt_interval=c,
+                tile=mixed["tile"], ckpt_interval=c, store_noise=mixed["store_noise"],
                 kernel_ms=1e3 * mixed["kernel_s"], alg_slots_per_particle_step=slots,
                 resample_fraction=r,
                 hbm_algorithmic_bytes_per_launch=hbm_bytes,
-                hbm_algorithmic_GBs=hbm_bytes / mixed["kernel_s"] / 1e9,
-                hbm_frac=hbm_bytes / mixed["kernel_s"] / 1e9 / PEAK_HBM_GBS,
+                hbm_design_bytes_per_launch=design_bytes,
+                hbm_design_GBs=design_bytes / mixed["kernel_s"] / 1e9,
+                hbm_design_frac=design_bytes / mixed["kernel_s"] / 1e9 / PEAK_HBM_GBS,
+                hbm_measured_frac=(traffic / mixed["kernel_s"] / 1e9 / PEAK_HBM_GBS
+                                   if traffic else None),
                 kernel_sources_sha=kernel_sources_sha())
 
     cpu = None

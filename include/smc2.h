@@ -91,6 +91,10 @@ typedef struct {
   int32_t tile;          /* launch shape: 0 = tuned default, else an index from smc2_tile_info */
   int32_t persistent;    /* 1: persistent grid pulling (s, i) items longest-series-first from an
                             on-device queue; 0: one workgroup per item in the same order */
+  int32_t store_noise;   /* 1: the forward sweep stores its reparameterised noise (drawn in
+                            advance, eq. reparam_epsilon) and the adjoint reads it back, at
+                            (T_max + 1) * d_x * MP values per item of extra scratch; 0: the
+                            adjoint regenerates it from the counter-based stream */
 } smc2_pf_opts;
 
 /* ---- context ------------------------------------------------------------------------------ */
@@ -134,7 +138,7 @@ smc2_status smc2_ctx_device_status(smc2_ctx *ctx, void *stream);
  * particle gradients inherited from the parent).  The gradient is computed in reverse mode: a
  * forward sweep that stores int32 ancestors at resampling steps and (x, log W) checkpoints
  * every ckpt_interval steps, then a backward sweep that recomputes each segment from its
- * checkpoint with the stored ancestors.
+ * checkpoint with the stored ancestors (and the stored noise with store_noise = 1).
  *
  *   T_len    host [S]: length of series s (0 <= T_len[s] <= T_max); y rows past it are ignored.
  *   theta    dev  [S][N][D] FP64.

@@ -1,9 +1,10 @@
 """Autotuner of the fused filter's launch shape and checkpoint interval.
 
 For a workload it times every built launch shape whose capacity fits the particle count
-(waves per workgroup x 64 x particles per lane = the next power of two >= M) and a few
-checkpoint intervals, each for a handful of launches timed with HIP events on the launch
-stream, and keeps the fastest.  Results are cached in a JSON file keyed by model, state and
+(waves per workgroup x 64 x particles per lane = the next power of two >= M), a few
+checkpoint intervals (the square root of T, a few steps, every step) and both ways the adjoint
+obtains the forward's noise (stored or regenerated), each for a handful of launches timed with
+HIP events on the launch stream, and keeps the fastest.  Results are cached in a JSON file keyed by model, state and
 parameter dimension, particle count, series-length and item-count buckets, precision and device
 name, so a later run on the same device reuses them.
 """
@@ -19,7 +20,8 @@ from . import smc2
 CACHE = os.environ.get("SMC2_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "smc2_autotune.json"))
 NUM_TILES = 18  # indices 1.. of the library's launch-shape table
-CKPT_CANDIDATES = (0, 8, 4)
+CKPT_CANDIDATES = (0, 8, 4, 1)
+NOISE_CANDIDATES = (1, 0)
 
 
 def _bucket(v):
@@ -29,9 +31,12 @@ def _bucket(v):
     return p
 
 
+VERSION = 2  # bump when the kernel changes enough to invalidate cached choices
+
+
 def key(w, precision, device_name):
-    return "|".join(str(v) for v in (w.kind, w.d, w.D, w.M, _bucket(w.T_max), _bucket(w.S * w.N),
-                                      precision, device_name))
+    return "|".join(str(v) for v in (VERSION, w.kind, w.d, w.D, w.M, _bucket(w.T_max),
+                                      _bucket(w.S * w.N), precision, device_name))
 
 
 def candidate_tiles(w):
@@ -47,11 +52,12 @@ def candidate_tiles(w):
     return out
 
 
-def time_config(w, precision, tile, ckpt, reps=3, seed_theta=0):
+def time_config(w, precision, tile, ckpt, store_noise=1, reps=3, seed_theta=0):
     """Mean duration (s) of the fused forward+adjoint over `reps` launches."""
     dev = torch.device("cuda:0")
     model = smc2.Model.from_workload(w)
-    opts = smc2.pf_opts(precision=precision, tile=tile, ckpt_interval=ckpt)
+    opts = smc2.pf_opts(precision=precision, tile=tile, ckpt_interval=ckpt,
+                        store_noise=store_noise)
     ctx = smc2.Context(model, opts, w.S, w.N, w.M, w.T_len, w.T_max)
     try:
         rng = np.random.default_rng(seed_theta)
@@ -75,7 +81,8 @@ def time_config(w, precision, tile, ckpt, reps=3, seed_theta=0):
 
 
 def tune(w, precision, reps=3, use_cache=True, verbose=False):
-    """Best (tile, ckpt) for workload w at `precision`; returns a dict with the timings."""
+    """Best (tile, ckpt, store_noise) for workload w at `precision`; returns a dict with the
+    timings."""
     name = torch.cuda.get_device_name(0)
     k = key(w, precision, name)
     cache = {}
@@ -91,20 +98,22 @@ def tune(w, precision, reps=3, use_cache=True, verbose=False):
     t0 = time.perf_counter()
     for tile in candidate_tiles(w):
         for ckpt in CKPT_CANDIDATES:
-            try:
-                s = time_config(w, precision, tile, ckpt, reps=reps)
-            except smc2.SMC2Error:
-                continue
-            trials.append((s, tile, ckpt))
-            if verbose:
-                print("[autotune] %s prec=%d tile=%d ckpt=%d: %.3f ms" % (w.name, precision, tile,
-                                                                        ckpt, 1e3 * s), flush=True)
+            for sn in NOISE_CANDIDATES:
+                try:
+                    s = time_config(w, precision, tile, ckpt, sn, reps=reps)
+                except smc2.SMC2Error:
+                    continue
+                trials.append((s, tile, ckpt, sn))
+                if verbose:
+                    print("[autotune] %s prec=%d tile=%d ckpt=%d noise=%d: %.3f ms" % (
+                        w.name, precision, tile, ckpt, sn, 1e3 * s), flush=True)
     if not trials:
         raise RuntimeError("no launch shape could run workload %s" % w.name)
-    s, tile, ckpt = min(trials)
-    res = dict(tile=int(tile), ckpt=int(ckpt), seconds=float(s), trials=len(trials),
-               tuning_seconds=time.perf_counter() - t0,
-               all=[dict(tile=int(t), ckpt=int(c), ms=1e3 * v) for v, t, c in sorted(trials)])
+    s, tile, ckpt, sn = min(trials)
+    res = dict(tile=int(tile), ckpt=int(ckpt), store_noise=int(sn), seconds=float(s),
+               trials=len(trials), tuning_seconds=time.perf_counter() - t0,
+               all=[dict(tile=int(t), ckpt=int(c), store_noise=int(n), ms=1e3 * v)
+                    for v, t, c, n in sorted(trials)])
     if use_cache:
         cache[k] = res
         try:

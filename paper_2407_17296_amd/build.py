@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libsmc2.so")
 
 SOURCES = ["smc2_api.hip", "pf_lg1d.hip", "pf_growth.hip", "pf_sv.hip", "pf_lgdiag.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + INCLUDE, "-I" + CSRC]
 

@@ -6,7 +6,9 @@
 //
 // R is the arithmetic type of propagation and weighting (double in the plain FP64 form, float
 // in the mixed form).  Parameters arrive in FP64 and are transformed once in FP64.  Gradient
-// contributions are accumulated into FP64 accumulators `tb` indexed like theta.
+// contributions are accumulated into FP64 accumulators `tb` indexed like theta.  The library is
+// compiled without floating-point contraction and every fused multiply-add here is written out,
+// so the adjoint's recomputation of a segment reproduces the forward sweep bit for bit.
 #pragma once
 
 #include "device_common.h"
@@ -20,21 +22,29 @@ __device__ __forceinline__ R mulz(R w, R v) {
   return w == (R)0 ? (R)0 : w * v;
 }
 
+// a * b + c rounded once
+__device__ __forceinline__ float fmar(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fmar(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+
 // x_t = a x + sx e;  y = x + sy w;  theta = (a, log sx, log sy);  x_0 ~ N(0, 1).
 template <typename R>
 struct ModelLG1D {
   static constexpr int DX = 1, NP = 3;
-  R a, sx, lsy, isy;
+  R a, sx, c0, isy;  // c0 = -log(2 pi)/2 - log sy
   __device__ void setup(const double *th) {
     a = (R)th[0];
     sx = (R)exp(th[1]);
-    lsy = (R)th[2];
+    c0 = (R)(-kHalfLog2Pi - th[2]);
     isy = (R)exp(-th[2]);
   }
   __device__ void per_step(int) {}
   __device__ void init(const R *e0, R *x) const { x[0] = e0[0]; }
   __device__ void init_adj(const R *, const R *, double *) const {}
-  __device__ void step(R *x, const R *e) const { x[0] = a * x[0] + sx * e[0]; }
+  __device__ void step(R *x, const R *e) const { x[0] = fmar(a, x[0], sx * e[0]); }
   // reverse of step: tb += F_theta^T xb;  xb <- F_x^T xb   (xp = state before the step)
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
     tb[0] += (double)mulz(xb[0], xp[0]);
@@ -43,13 +53,13 @@ struct ModelLG1D {
   }
   __device__ R logg(const R *y, const R *x) const {
     const R r = (y[0] - x[0]) * isy;
-    return (R)(-kHalfLog2Pi) - lsy - (R)0.5 * r * r;
+    return fmar((R)-0.5 * r, r, c0);
   }
   // xb += wb d lambda/dx;  tb += wb d lambda/dtheta
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
     const R r = (y[0] - x[0]) * isy;
     xb[0] += mulz(wb, r * isy);
-    tb[2] += (double)mulz(wb, r * r - (R)1);
+    tb[2] += (double)mulz(wb, fmar(r, r, (R)-1));
   }
 };
 
@@ -58,12 +68,12 @@ struct ModelLG1D {
 template <typename R, int D_X>
 struct ModelLGDiag {
   static constexpr int DX = D_X, NP = D_X + 2;
-  R A[D_X], sx, lsy, isy;
+  R A[D_X], sx, c0, isy;  // c0 = d (-log(2 pi)/2 - log sy)
   __device__ void setup(const double *th) {
 #pragma unroll
     for (int q = 0; q < D_X; ++q) A[q] = (R)th[q];
     sx = (R)exp(th[D_X]);
-    lsy = (R)th[D_X + 1];
+    c0 = (R)((double)D_X * (-kHalfLog2Pi - th[D_X + 1]));
     isy = (R)exp(-th[D_X + 1]);
   }
   __device__ void per_step(int) {}
@@ -74,7 +84,7 @@ struct ModelLGDiag {
   __device__ void init_adj(const R *, const R *, double *) const {}
   __device__ void step(R *x, const R *e) const {
 #pragma unroll
-    for (int q = 0; q < D_X; ++q) x[q] = A[q] * x[q] + sx * e[q];
+    for (int q = 0; q < D_X; ++q) x[q] = fmar(A[q], x[q], sx * e[q]);
   }
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
     R ssx = (R)0;
@@ -87,13 +97,13 @@ struct ModelLGDiag {
     tb[D_X] += (double)(ssx * sx);
   }
   __device__ R logg(const R *y, const R *x) const {
-    R acc = (R)0;
+    R s2 = (R)0;
 #pragma unroll
     for (int q = 0; q < D_X; ++q) {
       const R r = (y[q] - x[q]) * isy;
-      acc += (R)(-kHalfLog2Pi) - lsy - (R)0.5 * r * r;
+      s2 = fmar(r, r, s2);
     }
-    return acc;
+    return fmar((R)-0.5, s2, c0);
   }
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
     R s2 = (R)0;
@@ -101,9 +111,9 @@ struct ModelLGDiag {
     for (int q = 0; q < D_X; ++q) {
       const R r = (y[q] - x[q]) * isy;
       xb[q] += mulz(wb, r * isy);
-      s2 += r * r - (R)1;
+      s2 = fmar(r, r, s2);
     }
-    tb[D_X + 1] += (double)mulz(wb, s2);
+    tb[D_X + 1] += (double)mulz(wb, s2 - (R)D_X);
   }
 };
 
@@ -112,10 +122,10 @@ struct ModelLGDiag {
 template <typename R>
 struct ModelGrowth {
   static constexpr int DX = 1, NP = 2;
-  R sx, lsy, isy, drive;
+  R sx, c0, isy, drive;  // c0 = -log(2 pi)/2 - log sy
   __device__ void setup(const double *th) {
     sx = (R)exp(th[0]);
-    lsy = (R)th[1];
+    c0 = (R)(-kHalfLog2Pi - th[1]);
     isy = (R)exp(-th[1]);
     drive = (R)0;
   }
@@ -125,22 +135,22 @@ struct ModelGrowth {
   __device__ void init_adj(const R *, const R *, double *) const {}
   __device__ void step(R *x, const R *e) const {
     const R v = x[0];
-    x[0] = (R)0.5 * v + (R)25 * v * frcp((R)1 + v * v) + drive + sx * e[0];
+    x[0] = fmar((R)0.5, v, (R)25 * v * frcp(fmar(v, v, (R)1))) + fmar(sx, e[0], drive);
   }
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
-    const R v = xp[0], iden = frcp((R)1 + v * v);
-    const R fx = (R)0.5 + (R)25 * ((R)1 - v * v) * (iden * iden);
+    const R v = xp[0], iden = frcp(fmar(v, v, (R)1));
+    const R fx = fmar((R)25 * fmar(-v, v, (R)1), iden * iden, (R)0.5);
     tb[0] += (double)mulz(xb[0], sx * e[0]);
     xb[0] = mulz(xb[0], fx);
   }
   __device__ R logg(const R *y, const R *x) const {
-    const R r = (y[0] - x[0] * x[0] * (R)0.05) * isy;
-    return (R)(-kHalfLog2Pi) - lsy - (R)0.5 * r * r;
+    const R r = fmar(-x[0] * x[0], (R)0.05, y[0]) * isy;
+    return fmar((R)-0.5 * r, r, c0);
   }
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
-    const R r = (y[0] - x[0] * x[0] * (R)0.05) * isy;
+    const R r = fmar(-x[0] * x[0], (R)0.05, y[0]) * isy;
     xb[0] += mulz(wb, r * isy * x[0] * (R)0.1);
-    tb[1] += (double)mulz(wb, r * r - (R)1);
+    tb[1] += (double)mulz(wb, fmar(r, r, (R)-1));
   }
 };
 
@@ -158,13 +168,15 @@ struct ModelSV {
     dsd0 = (R)(exp(th[2]) * sinh(th[1]));
   }
   __device__ void per_step(int) {}
-  __device__ void init(const R *e0, R *x) const { x[0] = mu + sd0 * e0[0]; }
+  __device__ void init(const R *e0, R *x) const { x[0] = fmar(sd0, e0[0], mu); }
   __device__ void init_adj(const R *e0, const R *xb, double *tb) const {
     tb[0] += (double)xb[0];
     tb[1] += (double)mulz(xb[0], dsd0 * e0[0]);
     tb[2] += (double)mulz(xb[0], sd0 * e0[0]);
   }
-  __device__ void step(R *x, const R *e) const { x[0] = mu + phi * (x[0] - mu) + s * e[0]; }
+  __device__ void step(R *x, const R *e) const {
+    x[0] = fmar(phi, x[0] - mu, fmar(s, e[0], mu));
+  }
   __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
     tb[0] += (double)(xb[0] * ((R)1 - phi));
     tb[1] += (double)mulz(xb[0], ((R)1 - phi * phi) * (xp[0] - mu));
@@ -172,10 +184,10 @@ struct ModelSV {
     xb[0] = phi * xb[0];
   }
   __device__ R logg(const R *y, const R *x) const {
-    return (R)(-kHalfLog2Pi) - (R)0.5 * x[0] - (R)0.5 * y[0] * y[0] * fexp(-x[0]);
+    return fmar((R)-0.5, fmar(y[0] * y[0], fexp(-x[0]), x[0]), (R)(-kHalfLog2Pi));
   }
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *) const {
-    xb[0] += mulz(wb, (R)(-0.5) + (R)0.5 * y[0] * y[0] * fexp(-x[0]));
+    xb[0] += mulz(wb, fmar((R)0.5 * y[0] * y[0], fexp(-x[0]), (R)-0.5));
   }
 };
 

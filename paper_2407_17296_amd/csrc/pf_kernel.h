@@ -3,13 +3,22 @@
 // Forward (paper Sec. II with the bootstrap proposal, eqs. prior_proposal and
 // priorproposalweight): for t = 1..T each particle slot j propagates with its own
 // reparameterised noise (eq. reparam_epsilon), is weighted by g, and the workgroup forms
-// s_t = log sum_j exp(lW_{t-1}^j + lambda_t^j) (a max and an FP64 sum), accumulates
-// loglik += s_t (eq. likelihood_pf_ step by step), normalises (eq. normalisedweights) and tests
-// ESS = 1 / sum W^2 (eq. ess).  Below the threshold (never at t = T) it resamples (App. B):
-// an FP64 inclusive prefix P of the weights, and offspring i takes the first parent m with
-// P_m >= u_i P_{M-1} (the paper's index kappa_i = sum_j [nu_i > c_j]), with systematic
-// u_i = (i + nu)/M or multinomial u_i = nu_i; equal weights after.  The int32 ancestors are
-// stored, and (x, log W) checkpoints are stored every c steps.
+// s_t = log sum_j exp(lW_{t-1}^j + lambda_t^j), accumulates loglik += s_t (eq. likelihood_pf_
+// step by step), normalises (eq. normalisedweights) and tests ESS = 1 / sum W^2 (eq. ess).
+// Below the threshold (never at t = T) it resamples (App. B): an FP64 inclusive prefix P of the
+// weights, and offspring i takes the first parent m with P_m >= u_i P_{M-1} (the paper's index
+// kappa_i = sum_j [nu_i > c_j]), with systematic u_i = (i + nu)/M or multinomial u_i = nu_i;
+// equal weights after.  The int32 ancestors are stored, and (x, log W) checkpoints are stored
+// every c steps.
+//
+// The log-sum-exp takes two workgroup exchanges per step: the maximum, then the FP64 sums of
+// exp(lw - max) (the total of a lane prefix scan that resampling reuses) and of their squares.
+// No logarithm is taken inside the step loop: the carried log-weights are shifted by the step's
+// maximum only, so their exponentials sum to S_t rather than one, and
+//   loglik = sum_t max_t + sum over resampled steps and T of log S_t
+// (between resampling steps the log S terms of the unnormalised carry cancel).  The logs of S_t
+// and the per-step log normalisers max_t + log S_t that the adjoint needs are formed after the
+// sweep, in parallel over the workgroup.
 //
 // Systematic resampling needs no search: the targets increase with i, so each parent m counts
 // C_m = #{i : target_i <= P_m} (an estimate corrected by evaluating the same FP64 comparisons),
@@ -19,7 +28,9 @@
 // Adjoint (the transpose of App. A's tangent recursion, eqs. dloglik..dxk, with App. B's rules
 // that resampled weights have zero derivative and a resampled particle inherits its parent's):
 // segments are processed last to first; each is recomputed forward from its checkpoint with the
-// stored ancestors and stored s_t into a segment buffer, then swept backward.  Because the
+// stored ancestors and stored s_t into a segment buffer, then swept backward.  The noise of the
+// forward sweep is either stored by it (the reparameterisation draws it in advance, eq.
+// reparam_epsilon) and read back, or regenerated from the counter-based stream.  Because the
 // normalised weights sum to one, the adjoint of the per-step log-weights between two resampling
 // steps is the normalised weight vector at the later one (or at T); it is carried per particle
 // as `wb`.  At a resampling step the state adjoint is scatter-added from offspring to parents.
@@ -53,14 +64,17 @@ struct PFArgs {
   int32_t *anc;         // [slots][t_ld][ld]
   uint8_t *flags;       // [slots][t_ld]
   void *ckpt_buf;       // [slots][nseg_max][DX+1][ld]  (R)
-  void *seg_buf;        // [slots][ckpt][2*DX+1][ld]    (R)
+  void *seg_buf;        // [slots][ckpt][rows][ld] (R): x before the step (DX rows), the noise
+                        // (DX rows, only without `noise`), the normalised weight (1 row)
+  void *noise;          // [slots][t_ld+1][DX][ld] (R) forward noise for the adjoint, or NULL
 };
 
-// Dynamic shared memory of one item: y as R [lds_T * DX], then s_t as double [lds_T], then the
-// flags as bytes [lds_T].
+// Dynamic shared memory of one item: y as R [lds_T * DX], then S_t (later max_t + log S_t) as
+// double [lds_T], then max_t as R [lds_T], then the flags as bytes [lds_T].
 template <typename R, int DX>
 __host__ __device__ constexpr size_t pf_dyn_lds_bytes(int lds_T) {
-  return ((size_t)lds_T * DX * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T * 8 + (size_t)lds_T;
+  return ((size_t)lds_T * DX * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T * 8 +
+         ((size_t)lds_T * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T;
 }
 
 // The filter's noise (counter contract): element g = j*DX + q of step t (t = 0: the initial
@@ -158,23 +172,24 @@ struct SysTargets {
   }
 };
 
-// Ancestors of this thread's offspring slots under systematic resampling: each parent marks
-// the first offspring it owns, and an exclusive max-scan over the markers hands every
-// offspring the last parent that started at or before it.  FAST: M fills the tile (a power of
-// two), so no slot is padding.
+// Ancestors of this thread's offspring slots under systematic resampling.  The weight prefix of
+// slot j0 + p is base + part_p (the exclusive prefix of the lane plus its running sum).  Each parent marks the first offspring it owns, and an exclusive max-scan over
+// the markers hands every offspring the last parent that started at or before it; a reader
+// clears its own markers after use.  FAST: M fills the tile (a power of two), so no slot is
+// padding.  `dummy` is a per-lane marker slot for parents that own nothing.
 template <bool FAST, int WAVES, int PPL, typename R>
-__device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, double off,
+__device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, double base,
                                                      const R (&ew)[PPL], int j0, int M,
                                                      int *sh_mark, int *sh_imax, int (&a)[PPL],
                                                      int dummy) {
   const double tot = tg.tot;
-  int prev = tg.upto<FAST>(fmin(off, tot));
+  int prev = tg.upto<FAST>(fmin(base, tot));
   double part = 0.0;
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     const int m = j0 + p;
     part += (double)ew[p];
-    const double P = (m == M - 1) ? tot : fmin(off + part, tot);
+    const double P = (m == M - 1) ? tot : fmin(base + part, tot);
     int cm = tg.upto<FAST>(P);
     if (!FAST && m >= M) cm = prev;
     atomicMax(&sh_mark[cm > prev ? prev : dummy], m);
@@ -185,6 +200,7 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     run = max(run, sh_mark[j0 + p]);
+    sh_mark[j0 + p] = -1;
     a[p] = run;
   }
   const int before = block_exclusive_max_scan<WAVES>(run, sh_imax);
@@ -193,22 +209,25 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
 }
 
 template <typename R, class Model, int WAVES, int PPL>
-__global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <= 4) ? 4 : 1) void pf_fwd_adj_kernel(PFArgs A) {
+__global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <= 4) ? 4 : 1)
+void pf_fwd_adj_kernel(PFArgs A) {
   constexpr int NT = WAVES * 64, MP = NT * PPL, DX = Model::DX, NP = Model::NP;
   constexpr double kNegInf = -__builtin_huge_val();
-  __shared__ double sh_P[MP];    // multinomial prefix
-  __shared__ R sh_X[2][MP];      // gather / adjoint-scatter staging (ping-pong)
-  __shared__ int sh_mark[MP + 1];  // systematic: first-offspring markers (+ a dummy slot)
-  __shared__ double sh_red[2][2 * WAVES + 2];
+  __shared__ double sh_P[MP];        // multinomial prefix
+  __shared__ R sh_X[2][MP];          // gather / adjoint-scatter staging (ping-pong)
+  __shared__ int sh_mark[MP + 64];   // systematic first-offspring markers + a dummy per lane
+  __shared__ double sh_ex[2][3 * WAVES];  // per-wave max and (sum, sum of squares), ping-pong
   __shared__ double sh_vec[WAVES * NP];
   __shared__ int sh_imax[WAVES];
   __shared__ int sh_item;
   extern __shared__ double sh_dyn[];
   R *sh_y = (R *)sh_dyn;
   double *sh_s = sh_dyn + ((size_t)A.lds_T * DX * sizeof(R) + 7) / 8;
-  uint8_t *sh_f = (uint8_t *)(sh_s + A.lds_T);
+  R *sh_mx = (R *)(sh_s + A.lds_T);
+  uint8_t *sh_f = (uint8_t *)(sh_s + A.lds_T + ((size_t)A.lds_T * sizeof(R) + 7) / 8);
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
   const int j0 = tid * PPL;
   const int M = A.M;
   const double Md = (double)M;
@@ -220,6 +239,7 @@ __global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <=
   const R lWeqR = (R)lWeq;
   const int c = A.ckpt;
   const bool systematic = A.resampler == 0;
+  const size_t LD = (size_t)A.ld;
 
   for (int round = 0;; ++round) {
     int idx;
@@ -258,42 +278,62 @@ __global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <=
       const double *ys = A.y + (size_t)s * A.T_max * DX;
       for (int r = tid; r < T * DX; r += NT) sh_y[r] = (R)ys[r];
     }
-    const size_t LD = (size_t)A.ld;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) sh_mark[j0 + p] = -1;
     R *ck = (R *)A.ckpt_buf + (size_t)slot * A.nseg_max * (DX + 1) * LD;
     int32_t *anc = A.anc + (size_t)slot * A.t_ld * LD;
     uint8_t *flg = A.flags + (size_t)slot * A.t_ld;
-    __syncthreads();  // y staged
+    R *nz = A.noise ? (R *)A.noise + (size_t)slot * (A.t_ld + 1) * DX * LD : nullptr;
+    __syncthreads();  // y staged, markers cleared
+
+    auto store_noise = [&](int t, const R (&e)[PPL][DX]) {
+#pragma unroll
+      for (int q = 0; q < DX; ++q)
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) nz[((size_t)t * DX + q) * LD + j0 + p] = e[p][q];
+    };
+    auto load_noise = [&](int t, R (&e)[PPL][DX]) {
+#pragma unroll
+      for (int q = 0; q < DX; ++q)
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) e[p][q] = nz[((size_t)t * DX + q) * LD + j0 + p];
+    };
 
     // ---- forward ------------------------------------------------------------------------------
     R x[PPL][DX], lW[PPL];
     {
       R e[PPL][DX];
       filter_noise<R, DX, PPL>(j0, fid, c3i, 0u, seed, e);
+      if (nz) store_noise(0, e);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         mdl.init(e[p], x[p]);
         lW[p] = lWeqR;
       }
     }
-    double ll = 0.0;
     bool dead = false;
     int nres = 0;
+    int ck_left = 0, ck_idx = 0;
     for (int t = 1; t <= T; ++t) {
-      if ((t - 1) % c == 0) {
-        R *cks = ck + (size_t)((t - 1) / c) * (DX + 1) * LD;
+      if (ck_left == 0) {
+        R *cks = ck + (size_t)ck_idx * (DX + 1) * LD;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
 #pragma unroll
           for (int q = 0; q < DX; ++q) cks[q * LD + j0 + p] = x[p][q];
           cks[DX * LD + j0 + p] = lW[p];
         }
+        ck_left = c;
+        ++ck_idx;
       }
+      --ck_left;
       mdl.per_step(t);
       const R *yv = sh_y + (size_t)(t - 1) * DX;
       double mloc = kNegInf;
       {
         R e[PPL][DX];
         filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
+        if (nz) store_noise(t, e);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
           mdl.step(x[p], e[p]);
@@ -303,45 +343,65 @@ __global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <=
           mloc = fmax(mloc, (double)v);
         }
       }
-      const double mx = block_max<WAVES>(mloc, sh_red[0]);
+      // log-sum-exp, exchange 1: the maximum
+      double *ex = sh_ex[t & 1];
+      {
+        const double mw = wave_max(mloc);
+        if (lane == 0) ex[wid] = mw;
+      }
+      __syncthreads();
+      double mx = ex[0];
+#pragma unroll
+      for (int w = 1; w < WAVES; ++w) mx = fmax(mx, ex[w]);
       if (mx == kNegInf) {  // no particle explains y_t
         dead = true;
         break;
       }
+      // exchange 2: FP64 sums of exp(lw - max) (as a lane prefix scan) and of their squares
+      const R mxR = (R)mx;
       R ew[PPL];
-      double S = 0.0, Q = 0.0;
+      double acc = 0.0, qacc = 0.0;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        ew[p] = fexp(lW[p] - (R)mx);
+        ew[p] = fexp(lW[p] - mxR);
         const double ed = (double)ew[p];
-        S += ed;
-        Q += ed * ed;
+        acc += ed;
+        qacc += ed * ed;
+        lW[p] = lW[p] - mxR;  // the carry: log-weights shifted by the maximum
       }
-      block_sum2<WAVES>(S, Q, sh_red[1]);
-      const double st = mx + log(S);
-      ll += st;
+      const double inc = wave_inclusive_sum(acc);
+      {
+        const double sw = readlane_f64(inc, 63), qw = wave_sum(qacc);
+        if (lane == 0) {
+          ex[WAVES + 2 * wid] = sw;
+          ex[WAVES + 2 * wid + 1] = qw;
+        }
+      }
+      __syncthreads();
+      double S = 0.0, Q = 0.0, off = 0.0;
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) lW[p] = lW[p] - (R)st;
-      const bool res = (t < T) && (S * S / Q < A.ess_thresh);
+      for (int w = 0; w < WAVES; ++w) {
+        if (w == wid) off = S;
+        S = S + ex[WAVES + 2 * w];
+        Q = Q + ex[WAVES + 2 * w + 1];
+      }
+      const bool res = (t < T) && (S * S < A.ess_thresh * Q);  // ESS = S^2 / Q (eq. ess)
       if (tid == 0) {
-        sh_s[t - 1] = st;
+        sh_s[t - 1] = S;
+        sh_mx[t - 1] = mxR;
         sh_f[t - 1] = res ? 1 : 0;
         flg[t - 1] = res ? 1 : 0;
       }
       if (!res) continue;
 
       // -- resampling (App. B) --
+      // prefix of the weights: P_j = (wave offset + lane prefix) + lane running sum to j
       R *sx = sh_X[nres & 1];
       ++nres;
-      double acc = 0.0;
+      const double base = off + dpp_f64<kDppWaveShr1>(0.0, inc);
+      const double tot = S;
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        acc += (double)ew[p];
-        sx[j0 + p] = x[p][0];
-        sh_mark[j0 + p] = -1;
-      }
-      double tot;
-      const double off = block_exclusive_scan<WAVES>(acc, sh_red[0], tot);
+      for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][0];
       int a[PPL];
       if (systematic) {
         SysTargets tg;
@@ -352,15 +412,17 @@ __global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <=
         tg.tot = tot;
         tg.inv_tot = 1.0 / tot;
         if (M == MP)
-          systematic_ancestors<true, WAVES, PPL>(tg, off, ew, j0, M, sh_mark, sh_imax, a, MP);
+          systematic_ancestors<true, WAVES, PPL>(tg, base, ew, j0, M, sh_mark, sh_imax, a,
+                                                 MP + lane);
         else
-          systematic_ancestors<false, WAVES, PPL>(tg, off, ew, j0, M, sh_mark, sh_imax, a, MP);
+          systematic_ancestors<false, WAVES, PPL>(tg, base, ew, j0, M, sh_mark, sh_imax, a,
+                                                  MP + lane);
       } else {
         double part = 0.0;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
           part += (double)ew[p];
-          sh_P[j0 + p] = off + part;
+          sh_P[j0 + p] = base + part;
         }
         double u[PPL];
         filter_uniforms<PPL>(j0, fid, c3r, (uint32_t)t, seed, u);
@@ -393,11 +455,24 @@ __global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <=
       if (gout && tid < NP) gout[tid] = 0.0;
       continue;
     }
-    if (tid == 0) A.loglik[item] = ll;
+    // loglik = sum_t max_t + sum over resampled steps and T of log S_t; the adjoint's per-step
+    // log normaliser max_t + log S_t replaces S_t in LDS
+    __syncthreads();  // S_t, max_t and the flags written by thread 0 are visible
+    {
+      double part = 0.0;
+      for (int t = 1 + tid; t <= T; t += NT) {
+        const double lS = log(sh_s[t - 1]), m = (double)sh_mx[t - 1];
+        part += (t == T || sh_f[t - 1]) ? m + lS : m;
+        sh_s[t - 1] = m + lS;
+      }
+      double v[1] = {part};
+      block_sum_vec<WAVES, 1>(v, sh_vec);
+      if (tid == 0) A.loglik[item] = v[0];
+    }
     if (!A.want_grad) continue;
 
     // ---- adjoint --------------------------------------------------------------------------
-    __syncthreads();  // s_t and flags written by thread 0 become visible to the workgroup
+    __syncthreads();  // the per-step log normalisers are visible to the workgroup
     R xb[PPL][DX], wb[PPL];
     double tb[NP];
 #pragma unroll
@@ -408,84 +483,88 @@ __global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <=
     }
 #pragma unroll
     for (int p = 0; p < NP; ++p) tb[p] = 0.0;
-    constexpr int ROW = 2 * DX + 1;
-    R *sg = (R *)A.seg_buf + (size_t)slot * c * ROW * LD;
     int pp = 0;  // ping-pong selector of the gather / scatter staging in sh_X
-    const int nseg = (T + c - 1) / c;
-    for (int seg = nseg - 1; seg >= 0; --seg) {
-      const int t0 = seg * c, t1 = min(T, t0 + c);
-      const R *cks = ck + (size_t)seg * (DX + 1) * LD;
+    // One reverse step t: the weight adjoint restarts at resampled steps and at T, the state
+    // adjoint is scatter-added from offspring to parents at resampled steps, then the step's
+    // observation and transition are differentiated.  xp / xn: state before / after the step.
+    auto reverse_step = [&](int t, const R (&xp)[PPL][DX], const R (&xn)[PPL][DX],
+                            const R (&ce)[PPL][DX], const R (&cw)[PPL], const int (&ca)[PPL]) {
+      const R *yv = sh_y + (size_t)(t - 1) * DX;
+      const bool res = t < T && sh_f[t - 1] != 0;
+      if (t == T) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
+      } else if (res) {
+        // offspring -> parent: xb_pre[m] = sum over offspring i with a_i = m of xb_post[i];
+        // a lane adds each run of its offspring that share a parent once.  The staging is
+        // zero before use and each reader zeroes what it read.
+#pragma unroll
+        for (int q = 0; q < DX; ++q) {
+          R *ss = sh_X[pp];
+          pp ^= 1;
+          int ra = ca[0];
+          R rs = (R)0;
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            const R v = (j0 + p < M) ? xb[p][q] : (R)0;
+            if (ca[p] != ra) {
+              if (rs != (R)0) atomicAdd(&ss[ra], rs);
+              ra = ca[p];
+              rs = (R)0;
+            }
+            rs += v;
+          }
+          if (rs != (R)0) atomicAdd(&ss[ra], rs);
+          __syncthreads();
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            xb[p][q] = ss[j0 + p];
+            ss[j0 + p] = (R)0;
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
+      }
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-        for (int q = 0; q < DX; ++q) x[p][q] = cks[q * LD + j0 + p];
-        lW[p] = cks[DX * LD + j0 + p];
+        mdl.logg_adj(yv, xn[p], wb[p], xb[p], tb);
+        mdl.step_adj(xp[p], ce[p], xb[p], tb);
       }
-      // recompute the segment with the stored ancestors and log normalisers
-      for (int t = t0 + 1; t <= t1; ++t) {
-        const bool res = sh_f[t - 1] != 0;
-        int a[PPL];
-        if (res)
+    };
+    auto zero_staging = [&]() {
+      __syncthreads();  // earlier readers of the staging are done
 #pragma unroll
-          for (int p = 0; p < PPL; ++p) a[p] = anc[(size_t)(t - 1) * LD + j0 + p];
-        mdl.per_step(t);
-        const R *yv = sh_y + (size_t)(t - 1) * DX;
-        R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
-        const R st = (R)sh_s[t - 1];
-        R e[PPL][DX];
-        filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-          for (int q = 0; q < DX; ++q) {
-            row[q * LD + j0 + p] = x[p][q];
-            row[(DX + q) * LD + j0 + p] = e[p][q];
-          }
-          mdl.step(x[p], e[p]);
-          R v = lW[p] + mdl.logg(yv, x[p]);
-          if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
-          lW[p] = v - st;
-        }
-        if (t == T || res) {
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) row[2 * DX * LD + j0 + p] = fexp(lW[p]);
-        }
-        if (res) {
-#pragma unroll
-          for (int q = 0; q < DX; ++q) {
-            R *sx = sh_X[pp];
-            pp ^= 1;
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][q];
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) x[p][q] = sx[a[p]];
-          }
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
-        }
+      for (int p = 0; p < PPL; ++p) {
+        sh_X[0][j0 + p] = (R)0;
+        sh_X[1][j0 + p] = (R)0;
       }
-      // reverse sweep over the segment; the rows (state before the step, noise, weight) and
-      // ancestors of step t - 1 are loaded while step t is processed
-      R nx[PPL][DX], ne[PPL][DX], nw[PPL];
+      __syncthreads();
+      pp = 0;
+    };
+
+    if (c == 1) {
+      // Every step's starting state (x, log W) is a checkpoint: one reverse sweep that reads
+      // the state before each step, rebuilds the step and its weight, and differentiates it.
+      zero_staging();
+      R nx[PPL][DX], nl[PPL], ne[PPL][DX];
       int na[PPL];
-      auto load_step = [&](int t) {
-        const R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
+      auto load_trace = [&](int t) {
+        const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
         const bool lres = t < T && sh_f[t - 1] != 0;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
 #pragma unroll
           for (int q = 0; q < DX; ++q) {
-            nx[p][q] = row[q * LD + j0 + p];
-            ne[p][q] = row[(DX + q) * LD + j0 + p];
+            nx[p][q] = cks[q * LD + j0 + p];
+            if (nz) ne[p][q] = nz[((size_t)t * DX + q) * LD + j0 + p];
           }
-          nw[p] = (t == T || lres) ? row[2 * DX * LD + j0 + p] : (R)0;
+          nl[p] = cks[DX * LD + j0 + p];
           na[p] = lres ? anc[(size_t)(t - 1) * LD + j0 + p] : 0;
         }
       };
-      load_step(t1);
-      for (int t = t1; t > t0; --t) {
-        R cx[PPL][DX], ce[PPL][DX], cw[PPL];
+      if (T > 0) load_trace(T);
+      for (int t = T; t >= 1; --t) {
+        R cx[PPL][DX], xn[PPL][DX], ce[PPL][DX], cl[PPL], cw[PPL];
         int ca[PPL];
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
@@ -494,60 +573,153 @@ __global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <=
             cx[p][q] = nx[p][q];
             ce[p][q] = ne[p][q];
           }
-          cw[p] = nw[p];
+          cl[p] = nl[p];
           ca[p] = na[p];
         }
-        if (t - 1 > t0) load_step(t - 1);
+        if (t > 1) load_trace(t - 1);
+        if (!nz) filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, ce);
         mdl.per_step(t);
         const R *yv = sh_y + (size_t)(t - 1) * DX;
-        const bool res = t < T && sh_f[t - 1] != 0;
-        if (t == T) {
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
-        } else if (res) {
-          // offspring -> parent: xb_pre[m] = sum over offspring i with a_i = m of xb_post[i];
-          // a lane adds each run of its offspring that share a parent once
-#pragma unroll
-          for (int q = 0; q < DX; ++q) {
-            R *ss = sh_X[pp];
-            pp ^= 1;
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) ss[j0 + p] = (R)0;
-            __syncthreads();
-            int ra = ca[0];
-            R rs = (R)0;
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-              const R v = (j0 + p < M) ? xb[p][q] : (R)0;
-              if (ca[p] != ra) {
-                if (rs != (R)0) atomicAdd(&ss[ra], rs);
-                ra = ca[p];
-                rs = (R)0;
-              }
-              rs += v;
-            }
-            if (rs != (R)0) atomicAdd(&ss[ra], rs);
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) xb[p][q] = ss[j0 + p];
-          }
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
-        }
+        const bool need_w = t == T || sh_f[t - 1] != 0;
+        const R st = (R)sh_s[t - 1];  // max_t + log S_t
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          R xc[DX];
 #pragma unroll
-          for (int q = 0; q < DX; ++q) xc[q] = cx[p][q];
-          mdl.step(xc, ce[p]);
-          mdl.logg_adj(yv, xc, wb[p], xb[p], tb);
-          mdl.step_adj(cx[p], ce[p], xb[p], tb);
+          for (int q = 0; q < DX; ++q) xn[p][q] = cx[p][q];
+          mdl.step(xn[p], ce[p]);
+          cw[p] = (R)0;
+          if (need_w) {
+            R v = cl[p] + mdl.logg(yv, xn[p]);
+            if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
+            cw[p] = fexp(v - st);
+          }
+        }
+        reverse_step(t, cx, xn, ce, cw, ca);
+      }
+    } else {
+      // segment rows of one step: x before the step (DX rows), the noise when it is not
+      // stored (DX rows), the normalised weight at resampled steps and at T (1 row)
+      const int ROW = nz ? DX + 1 : 2 * DX + 1;
+      const int WROW = ROW - 1;
+      R *sg = (R *)A.seg_buf + (size_t)slot * c * (2 * DX + 1) * LD;
+      const int nseg = (T + c - 1) / c;
+      for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int t0 = seg * c, t1 = min(T, t0 + c);
+        const R *cks = ck + (size_t)seg * (DX + 1) * LD;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+#pragma unroll
+          for (int q = 0; q < DX; ++q) x[p][q] = cks[q * LD + j0 + p];
+          lW[p] = cks[DX * LD + j0 + p];
+        }
+        // recompute the segment with the stored ancestors and log normalisers
+        R ne[PPL][DX];
+        if (nz) load_noise(t0 + 1, ne);
+        for (int t = t0 + 1; t <= t1; ++t) {
+          const bool res = sh_f[t - 1] != 0;
+          int a[PPL];
+          if (res)
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) a[p] = anc[(size_t)(t - 1) * LD + j0 + p];
+          R e[PPL][DX];
+          if (nz) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p)
+#pragma unroll
+              for (int q = 0; q < DX; ++q) e[p][q] = ne[p][q];
+            if (t < t1) load_noise(t + 1, ne);
+          } else {
+            filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
+          }
+          mdl.per_step(t);
+          const R *yv = sh_y + (size_t)(t - 1) * DX;
+          R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
+          const R st = (R)sh_s[t - 1], mt = sh_mx[t - 1];  // max_t + log S_t, max_t
+          R wv[PPL];
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+#pragma unroll
+            for (int q = 0; q < DX; ++q) {
+              row[q * LD + j0 + p] = x[p][q];
+              if (!nz) row[(DX + q) * LD + j0 + p] = e[p][q];
+            }
+            mdl.step(x[p], e[p]);
+            R v = lW[p] + mdl.logg(yv, x[p]);
+            if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
+            wv[p] = v;
+            lW[p] = v - mt;
+          }
+          if (t == T || res) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) row[WROW * LD + j0 + p] = fexp(wv[p] - st);
+          }
+          if (res) {
+#pragma unroll
+            for (int q = 0; q < DX; ++q) {
+              R *sx = sh_X[pp];
+              pp ^= 1;
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][q];
+              __syncthreads();
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) x[p][q] = sx[a[p]];
+            }
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
+          }
+        }
+        zero_staging();
+        // reverse sweep over the segment; the rows (state before the step, noise, weight) and
+        // ancestors of step t - 1 are loaded while step t is processed
+        R nx[PPL][DX], nw[PPL];
+        int na[PPL];
+        auto load_step = [&](int t) {
+          const R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
+          const bool lres = t < T && sh_f[t - 1] != 0;
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+#pragma unroll
+            for (int q = 0; q < DX; ++q) {
+              nx[p][q] = row[q * LD + j0 + p];
+              ne[p][q] = nz ? nz[((size_t)t * DX + q) * LD + j0 + p]
+                            : row[(DX + q) * LD + j0 + p];
+            }
+            nw[p] = (t == T || lres) ? row[WROW * LD + j0 + p] : (R)0;
+            na[p] = lres ? anc[(size_t)(t - 1) * LD + j0 + p] : 0;
+          }
+        };
+        load_step(t1);
+        for (int t = t1; t > t0; --t) {
+          R cx[PPL][DX], xn[PPL][DX], ce[PPL][DX], cw[PPL];
+          int ca[PPL];
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+#pragma unroll
+            for (int q = 0; q < DX; ++q) {
+              cx[p][q] = nx[p][q];
+              ce[p][q] = ne[p][q];
+            }
+            cw[p] = nw[p];
+            ca[p] = na[p];
+          }
+          if (t - 1 > t0) load_step(t - 1);
+          mdl.per_step(t);
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+#pragma unroll
+            for (int q = 0; q < DX; ++q) xn[p][q] = cx[p][q];
+            mdl.step(xn[p], ce[p]);
+          }
+          reverse_step(t, cx, xn, ce, cw, ca);
         }
       }
     }
     {
       R e[PPL][DX];
-      filter_noise<R, DX, PPL>(j0, fid, c3i, 0u, seed, e);
+      if (nz)
+        load_noise(0, e);
+      else
+        filter_noise<R, DX, PPL>(j0, fid, c3i, 0u, seed, e);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) mdl.init_adj(e[p], xb[p], tb);
     }

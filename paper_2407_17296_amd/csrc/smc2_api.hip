@@ -128,7 +128,7 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 struct Layout {
   int MP, c, nseg, slots;
-  size_t anc, flags, ckpt, seg, outer, total;
+  size_t anc, flags, ckpt, seg, noise, outer, total;
 };
 
 }  // namespace
@@ -146,7 +146,7 @@ struct smc2_ctx {
   int32_t *T_len_dev = nullptr, *order_dev = nullptr;
   int32_t *anc = nullptr;
   uint8_t *flags = nullptr;
-  void *ckpt = nullptr, *seg = nullptr;
+  void *ckpt = nullptr, *seg = nullptr, *noise = nullptr;
   double *outer_scratch = nullptr;
   uint32_t *queue = nullptr;
   int32_t *status = nullptr;
@@ -162,7 +162,7 @@ struct smc2_ctx {
     T_len_dev = order_dev = anc = status = nullptr;
     flags = nullptr;
     outer_scratch = nullptr;
-    ckpt = seg = nullptr;
+    ckpt = seg = noise = nullptr;
     queue = nullptr;
     reserved = false;
   }
@@ -191,6 +191,8 @@ smc2_status check_opts(const smc2_pf_opts *o) {
     return fail(SMC2_E_INVALID_ARG, "ess_frac must be finite and >= 0");
   if (o->ckpt_interval < 0) return fail(SMC2_E_INVALID_ARG, "ckpt_interval must be >= 0");
   if (o->tile < 0 || o->tile >= kNumTiles) return fail(SMC2_E_INVALID_ARG, "unknown tile");
+  if (o->store_noise != 0 && o->store_noise != 1)
+    return fail(SMC2_E_INVALID_ARG, "store_noise must be 0 or 1");
   return SMC2_OK;
 }
 
@@ -212,8 +214,10 @@ smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, in
   L.flags = al((size_t)L.slots * Tc);
   L.ckpt = al((size_t)L.slots * L.nseg * (dx + 1) * L.MP * rs);
   L.seg = o->want_grad ? al((size_t)L.slots * L.c * (2 * dx + 1) * L.MP * rs) : 256;
+  L.noise = (o->want_grad && o->store_noise)
+                ? al((size_t)L.slots * (Tc + 1) * dx * L.MP * rs) : 256;
   L.outer = al((size_t)items * (2 * m->D + 2) * 8);
-  L.total = L.anc + L.flags + L.ckpt + L.seg + L.outer + al(items * 4) * 2 +
+  L.total = L.anc + L.flags + L.ckpt + L.seg + L.noise + L.outer + al(items * 4) * 2 +
             al((size_t)S * 4) + 512;
   return SMC2_OK;
 }
@@ -332,6 +336,7 @@ smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_
   GRAB(L.flags, ctx->flags, uint8_t *);
   GRAB(L.ckpt, ctx->ckpt, void *);
   GRAB(L.seg, ctx->seg, void *);
+  GRAB(L.noise, ctx->noise, void *);
   GRAB(L.outer, ctx->outer_scratch, double *);
   GRAB(items * 4, ctx->order_dev, int32_t *);
   GRAB((size_t)S * 4, ctx->T_len_dev, int32_t *);
@@ -395,9 +400,10 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
     return fail(SMC2_E_INVALID_ARG, "model differs from the reservation");
   if (opts->precision != ctx->opts.precision || opts->persistent != ctx->opts.persistent ||
       opts->ckpt_interval != ctx->opts.ckpt_interval ||
+      (opts->want_grad && opts->store_noise != ctx->opts.store_noise) ||
       (opts->want_grad && !ctx->opts.want_grad))
-    return fail(SMC2_E_INVALID_ARG, "precision, persistence, checkpoint interval or gradient "
-                                    "differ from the reservation");
+    return fail(SMC2_E_INVALID_ARG, "precision, persistence, checkpoint interval, noise "
+                                    "storage or gradient differ from the reservation");
   if (S != ctx->S || N != ctx->N || M > ctx->M || next_pow2(M) > ctx->L.MP || T_max > ctx->T_max)
     return fail(SMC2_E_INVALID_ARG, "sizes differ from or exceed the reservation");
   for (int s = 0; s < S; ++s) {
@@ -440,6 +446,7 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
   a.flags = ctx->flags;
   a.ckpt_buf = ctx->ckpt;
   a.seg_buf = ctx->seg;
+  a.noise = (opts->want_grad && opts->store_noise) ? ctx->noise : nullptr;
   int grid = items;
   if (opts->persistent) {
     grid = std::min(items, std::min(ctx->L.slots, ctx->num_cus * k->occupancy(a.lds_T)));

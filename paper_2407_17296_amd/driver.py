@@ -38,13 +38,13 @@ class SMC2Run:
 
     def __init__(self, w, precision=smc2.MIXED, resampler=smc2.SYSTEMATIC, ess_frac=0.5,
                  ckpt_interval=0, tile=0, persistent=0, random_walk=0, gamma=None, device=0,
-                 seed=None):
+                 seed=None, store_noise=1):
         self.w = w
         self.dev = torch.device("cuda", device)
         self.model = smc2.Model.from_workload(w)
         self.opts = smc2.pf_opts(precision=precision, resampler=resampler, ess_frac=ess_frac,
                                  ckpt_interval=ckpt_interval, want_grad=1, tile=tile,
-                                 persistent=persistent)
+                                 persistent=persistent, store_noise=store_noise)
         self.gamma = float(w.gamma if gamma is None else gamma)
         self.random_walk = int(random_walk)
         self.seed = int(w.seed if seed is None else seed)

@@ -39,7 +39,7 @@ class smc2_pf_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("resampler", ctypes.c_int32),
                 ("ess_frac", ctypes.c_double), ("ckpt_interval", ctypes.c_int32),
                 ("want_grad", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("store_noise", ctypes.c_int32)]
 
 
 class smc2_population(ctypes.Structure):
@@ -133,9 +133,9 @@ class Model:
 
 
 def pf_opts(precision=FP64, resampler=SYSTEMATIC, ess_frac=0.5, ckpt_interval=0, want_grad=1,
-            tile=0, persistent=0):
+            tile=0, persistent=0, store_noise=1):
     return smc2_pf_opts(int(precision), int(resampler), float(ess_frac), int(ckpt_interval),
-                        int(want_grad), int(tile), int(persistent))
+                        int(want_grad), int(tile), int(persistent), int(store_noise))
 
 
 # ---- entry points (same names as the C ABI) ----------------------------------------------------

@@ -13,15 +13,17 @@ def say(msg):
 
 
 def gpu_pf(w, theta, precision=smc2.FP64, resampler=smc2.SYSTEMATIC, ess_frac=0.5, ckpt=0,
-           k=1, tile=0, persistent=0, want_grad=1, trace_items=()):
+           k=1, tile=0, persistent=0, want_grad=1, trace_items=(), store_noise=1):
     """Run the fused filter on every (s, i) of workload w at parameters theta [S][N][D]."""
     import torch
     dev = torch.device("cuda:0")
     model = smc2.Model.from_workload(w)
     opts = smc2.pf_opts(precision=precision, resampler=resampler, ess_frac=ess_frac,
-                        ckpt_interval=ckpt, want_grad=want_grad, tile=tile, persistent=persistent)
-    say("  gpu_pf %s S=%d N=%d M=%d T_max=%d prec=%d res=%d tile=%d pers=%d ckpt=%d" % (
-        w.name, w.S, w.N, w.M, w.T_max, precision, resampler, tile, persistent, ckpt))
+                        ckpt_interval=ckpt, want_grad=want_grad, tile=tile, persistent=persistent,
+                        store_noise=store_noise)
+    say("  gpu_pf %s S=%d N=%d M=%d T_max=%d prec=%d res=%d tile=%d pers=%d ckpt=%d noise=%d" % (
+        w.name, w.S, w.N, w.M, w.T_max, precision, resampler, tile, persistent, ckpt,
+        store_noise))
     ctx = smc2.Context(model, opts, w.S, w.N, w.M, w.T_len, w.T_max)
     th = torch.tensor(np.ascontiguousarray(theta), dtype=torch.float64, device=dev)
     y = torch.tensor(w.y, dtype=torch.float64, device=dev).contiguous()

@@ -50,21 +50,25 @@ def _check_fp64(oracle, w, theta, ll, g, traces, k=1, resampler=0, ess_frac=0.5,
     assert gated >= min_gated * len(items)
 
 
+@pytest.mark.parametrize("store_noise", [1, 0])
 @pytest.mark.parametrize("resampler", [smc2.SYSTEMATIC, smc2.MULTINOMIAL])
-def test_fp64_small_lg1d_all_items(oracle, resampler):
+def test_fp64_small_lg1d_all_items(oracle, resampler, store_noise):
     w = synth.make(0)
     theta = synth.prior_draws(w)
     items = [(0, i) for i in range(w.N)]
-    ll, g, tr = gpu_pf(w, theta, resampler=resampler, k=2, trace_items=items)
+    ll, g, tr = gpu_pf(w, theta, resampler=resampler, k=2, trace_items=items,
+                       store_noise=store_noise)
     _check_fp64(oracle, w, theta, ll, g, tr, k=2, resampler=resampler)
 
 
-def test_fp64_growth_ragged_particles_and_segments(oracle):
-    """M = 100 (a 128-particle tile with a ragged tail), T = 37, checkpoints every 5 steps."""
+@pytest.mark.parametrize("ckpt", [5, 1])
+def test_fp64_growth_ragged_particles_and_segments(oracle, ckpt):
+    """M = 100 (a 128-particle tile with a ragged tail), T = 37, checkpoints every 5 steps
+    (a ragged last segment) or at every step (the adjoint recomputes nothing)."""
     w = synth.make(3, N=6, M=100, T=37)
     theta = spread_theta(w, 0.3, seed=1)
     items = [(0, i) for i in range(w.N)]
-    ll, g, tr = gpu_pf(w, theta, ckpt=5, k=4, trace_items=items)
+    ll, g, tr = gpu_pf(w, theta, ckpt=ckpt, k=4, trace_items=items)
     _check_fp64(oracle, w, theta, ll, g, tr, k=4)
 
 
@@ -142,13 +146,52 @@ def test_fp64_tiles_agree(oracle):
         assert dl <= 2e-12 and dg <= 2e-9, tile
 
 
-def test_fp64_persistent_equals_grid():
+@pytest.mark.parametrize("ckpt", [0, 1])
+def test_fp64_persistent_equals_grid(ckpt):
     w = synth.make(3, N=300, M=512, T=60)
     theta = spread_theta(w, 0.3, seed=8)
-    a = gpu_pf(w, theta, k=2, persistent=0)
-    b = gpu_pf(w, theta, k=2, persistent=1)
+    a = gpu_pf(w, theta, k=2, persistent=0, ckpt=ckpt)
+    b = gpu_pf(w, theta, k=2, persistent=1, ckpt=ckpt)
     assert np.array_equal(a[0], b[0])
     assert np.allclose(a[1], b[1], rtol=1e-12, atol=1e-12)
+
+
+def test_fp64_checkpoint_intervals_agree(oracle):
+    """Every checkpoint interval (every step, a few steps, the square root of T) yields the
+    same estimate and the same gradient up to the scatter's summation order."""
+    w = synth.make(4, S=3, N=4, M=256, T=40)
+    w.T_len = np.array([40, 17, 33], dtype=np.int32)
+    theta = spread_theta(w, 0.3, seed=10)
+    ref = gpu_pf(w, theta, k=2, ckpt=0)
+    for ckpt in (1, 3, 8):
+        ll, g, _ = gpu_pf(w, theta, k=2, ckpt=ckpt)
+        assert np.array_equal(ll, ref[0]), ckpt
+        worst = max(rel_err(g[s, i], ref[1][s, i]) for s in range(w.S) for i in range(w.N))
+        say("  ckpt %d vs sqrt(T): max relative gradient difference %.1e" % (ckpt, worst))
+        assert worst <= 1e-12, ckpt
+
+
+@pytest.mark.parametrize("precision", [smc2.FP64, smc2.MIXED])
+@pytest.mark.parametrize("index,kw,ckpt,spread", [
+    (3, dict(N=6, M=100, T=37), 5, 0.3),
+    (3, dict(N=6, M=100, T=37), 1, 0.3),
+    (4, dict(S=3, N=4, M=256, T=40), 0, 0.3),
+    (2, dict(N=3, M=64, T=12), 4, 0.05),
+])
+def test_stored_and_regenerated_noise_agree(index, kw, ckpt, spread, precision):
+    """The adjoint reads back the forward's stored noise or regenerates it from the counter
+    stream: the same numbers either way.  The forward sweep is the same code, so the estimates
+    agree bit for bit; the gradients agree up to the order in which the adjoint's scatter-add
+    to shared parents lands (workgroup atomics), i.e. to rounding."""
+    w = synth.make(index, **kw)
+    theta = spread_theta(w, spread, seed=9)
+    a = gpu_pf(w, theta, precision=precision, ckpt=ckpt, k=2, store_noise=1)
+    b = gpu_pf(w, theta, precision=precision, ckpt=ckpt, k=2, store_noise=0)
+    assert np.array_equal(a[0], b[0])
+    tol = 1e-12 if precision == smc2.FP64 else 1e-5
+    worst = max(rel_err(a[1][s, i], b[1][s, i]) for s in range(w.S) for i in range(w.N))
+    say("  stored vs regenerated noise: max relative gradient difference %.1e" % worst)
+    assert worst <= tol
 
 
 # ------------------------------------------------------------------- mixed precision ----
