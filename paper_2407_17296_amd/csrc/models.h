@@ -6,7 +6,8 @@
 //
 // R is the arithmetic type of propagation and weighting (double in the plain FP64 form, float
 // in the mixed form).  Parameters arrive in FP64 and are transformed once in FP64.  Gradient
-// contributions are accumulated into FP64 accumulators `tb` indexed like theta.  The library is
+// contributions are added into accumulators `tb` indexed like theta (type Acc: the kernel
+// sums a step's particles in R and carries the total in FP64).  The library is
 // compiled without floating-point contraction and every fused multiply-add here is written out,
 // so the adjoint's recomputation of a segment reproduces the forward sweep bit for bit.
 #pragma once
@@ -46,9 +47,10 @@ struct ModelLG1D {
   __device__ void init_adj(const R *, const R *, double *) const {}
   __device__ void step(R *x, const R *e) const { x[0] = fmar(a, x[0], sx * e[0]); }
   // reverse of step: tb += F_theta^T xb;  xb <- F_x^T xb   (xp = state before the step)
-  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
-    tb[0] += (double)mulz(xb[0], xp[0]);
-    tb[1] += (double)mulz(xb[0], sx * e[0]);
+  template <typename Acc>
+  __device__ void step_adj(const R *xp, const R *e, R *xb, Acc *tb) const {
+    tb[0] += (Acc)mulz(xb[0], xp[0]);
+    tb[1] += (Acc)mulz(xb[0], sx * e[0]);
     xb[0] = a * xb[0];
   }
   __device__ R logg(const R *y, const R *x) const {
@@ -56,10 +58,11 @@ struct ModelLG1D {
     return fmar((R)-0.5 * r, r, c0);
   }
   // xb += wb d lambda/dx;  tb += wb d lambda/dtheta
-  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
+  template <typename Acc>
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, Acc *tb) const {
     const R r = (y[0] - x[0]) * isy;
     xb[0] += mulz(wb, r * isy);
-    tb[2] += (double)mulz(wb, fmar(r, r, (R)-1));
+    tb[2] += (Acc)mulz(wb, fmar(r, r, (R)-1));
   }
 };
 
@@ -86,15 +89,16 @@ struct ModelLGDiag {
 #pragma unroll
     for (int q = 0; q < D_X; ++q) x[q] = fmar(A[q], x[q], sx * e[q]);
   }
-  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
+  template <typename Acc>
+  __device__ void step_adj(const R *xp, const R *e, R *xb, Acc *tb) const {
     R ssx = (R)0;
 #pragma unroll
     for (int q = 0; q < D_X; ++q) {
-      tb[q] += (double)mulz(xb[q], xp[q]);
+      tb[q] += (Acc)mulz(xb[q], xp[q]);
       ssx += mulz(xb[q], e[q]);
       xb[q] = A[q] * xb[q];
     }
-    tb[D_X] += (double)(ssx * sx);
+    tb[D_X] += (Acc)(ssx * sx);
   }
   __device__ R logg(const R *y, const R *x) const {
     R s2 = (R)0;
@@ -105,7 +109,8 @@ struct ModelLGDiag {
     }
     return fmar((R)-0.5, s2, c0);
   }
-  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
+  template <typename Acc>
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, Acc *tb) const {
     R s2 = (R)0;
 #pragma unroll
     for (int q = 0; q < D_X; ++q) {
@@ -113,7 +118,7 @@ struct ModelLGDiag {
       xb[q] += mulz(wb, r * isy);
       s2 = fmar(r, r, s2);
     }
-    tb[D_X + 1] += (double)mulz(wb, s2 - (R)D_X);
+    tb[D_X + 1] += (Acc)mulz(wb, s2 - (R)D_X);
   }
 };
 
@@ -137,20 +142,22 @@ struct ModelGrowth {
     const R v = x[0];
     x[0] = fmar((R)0.5, v, (R)25 * v * frcp(fmar(v, v, (R)1))) + fmar(sx, e[0], drive);
   }
-  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
+  template <typename Acc>
+  __device__ void step_adj(const R *xp, const R *e, R *xb, Acc *tb) const {
     const R v = xp[0], iden = frcp(fmar(v, v, (R)1));
     const R fx = fmar((R)25 * fmar(-v, v, (R)1), iden * iden, (R)0.5);
-    tb[0] += (double)mulz(xb[0], sx * e[0]);
+    tb[0] += (Acc)mulz(xb[0], sx * e[0]);
     xb[0] = mulz(xb[0], fx);
   }
   __device__ R logg(const R *y, const R *x) const {
     const R r = fmar(-x[0] * x[0], (R)0.05, y[0]) * isy;
     return fmar((R)-0.5 * r, r, c0);
   }
-  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *tb) const {
+  template <typename Acc>
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, Acc *tb) const {
     const R r = fmar(-x[0] * x[0], (R)0.05, y[0]) * isy;
     xb[0] += mulz(wb, r * isy * x[0] * (R)0.1);
-    tb[1] += (double)mulz(wb, fmar(r, r, (R)-1));
+    tb[1] += (Acc)mulz(wb, fmar(r, r, (R)-1));
   }
 };
 
@@ -177,16 +184,18 @@ struct ModelSV {
   __device__ void step(R *x, const R *e) const {
     x[0] = fmar(phi, x[0] - mu, fmar(s, e[0], mu));
   }
-  __device__ void step_adj(const R *xp, const R *e, R *xb, double *tb) const {
-    tb[0] += (double)(xb[0] * ((R)1 - phi));
-    tb[1] += (double)mulz(xb[0], ((R)1 - phi * phi) * (xp[0] - mu));
-    tb[2] += (double)mulz(xb[0], s * e[0]);
+  template <typename Acc>
+  __device__ void step_adj(const R *xp, const R *e, R *xb, Acc *tb) const {
+    tb[0] += (Acc)(xb[0] * ((R)1 - phi));
+    tb[1] += (Acc)mulz(xb[0], ((R)1 - phi * phi) * (xp[0] - mu));
+    tb[2] += (Acc)mulz(xb[0], s * e[0]);
     xb[0] = phi * xb[0];
   }
   __device__ R logg(const R *y, const R *x) const {
     return fmar((R)-0.5, fmar(y[0] * y[0], fexp(-x[0]), x[0]), (R)(-kHalfLog2Pi));
   }
-  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, double *) const {
+  template <typename Acc>
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, Acc *) const {
     xb[0] += mulz(wb, fmar((R)0.5 * y[0] * y[0], fexp(-x[0]), (R)-0.5));
   }
 };

@@ -152,13 +152,18 @@ struct SysTargets {
     return FAST ? ((double)i + nu) * inv_Md * tot : ((double)i + nu) / Md * tot;
   }
   // C = #{i in [0, M) : at(i) <= P}: the targets increase with i, so C is the first i whose
-  // target exceeds P.  The estimate g from P / tot is checked with the exact comparisons
-  // at(g - 1) <= P < at(g), which need no special cases at g = 0 (at(-1) <= 0) or g = M
-  // (at(M) > tot > P); a wrong estimate falls back to bisection.
+  // target exceeds P.  Near a tie the estimate g from P / tot is checked with the exact
+  // comparisons at(g - 1) <= P < at(g), which need no special cases at g = 0 (at(-1) <= 0) or
+  // g = M (at(M) > tot > P); a wrong estimate falls back to bisection.
+  // The estimate z = P M / tot - nu carries a few ulp; unless it lies within kTieMargin of an
+  // integer, floor(z) + 1 is the count and the comparisons are skipped.
+  static constexpr double kTieMargin = 1e-9;
   template <bool FAST>
   __device__ int upto(double P) const {
     if (!(P < tot)) return M;
-    const int g = (int)fmin(fmax(floor(P * inv_tot * Md - nu) + 1.0, 0.0), Md);
+    const double z = P * inv_tot * Md - nu, fz = floor(z), fr = z - fz;
+    const int g = (int)fmin(fmax(fz + 1.0, 0.0), Md);
+    if (fr > kTieMargin && fr < 1.0 - kTieMargin) return g;
     if (at<FAST>(g - 1) <= P && at<FAST>(g) > P) return g;
     int lo = 0, hi = M;
     while (lo < hi) {
@@ -525,11 +530,18 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
       }
+      // the lane's particles add their parameter adjoints in R; the step total joins the FP64
+      // accumulator
+      R tp[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) tp[k] = (R)0;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        mdl.logg_adj(yv, xn[p], wb[p], xb[p], tb);
-        mdl.step_adj(xp[p], ce[p], xb[p], tb);
+        mdl.logg_adj(yv, xn[p], wb[p], xb[p], tp);
+        mdl.step_adj(xp[p], ce[p], xb[p], tp);
       }
+#pragma unroll
+      for (int k = 0; k < NP; ++k) tb[k] += (double)tp[k];
     };
     auto zero_staging = [&]() {
       __syncthreads();  // earlier readers of the staging are done
