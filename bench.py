@@ -24,31 +24,34 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Peak figures of one MI355X (published): HBM3E bandwidth, and the vector-ALU issue rate with
-# packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-slots/s
-# (the FP32 vector rate without packed math, 78.6 TFLOP/s counting an FMA as two).
+# Peak figures of one MI355X (published): HBM3E bandwidth, and the FP32 vector issue rate with
+# packed FP32 disabled: 256 CUs x 128 FP32 lanes per clock x 2.4 GHz = 78.6 T lane-slots/s
+# (the published 157.3 TFLOP/s FP32 vector rate, counting an FMA as two).
 PEAK_HBM_GBS = 8000.0
-PEAK_VALU_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12  # T wave-lane instructions per second
+PEAK_VALU_TSLOTS = 256 * 128 * 2.4e9 / 1e12  # T FP32 lane-slots per second
 
 # Algorithmic VALU work per particle-step of the CRN-PF forward sweep and its adjoint for d = 1,
-# in issue slots of a direct implementation of the method's arithmetic (itemised in the design doc).
-# Full-rate instructions take one slot per lane; quarter-rate ones (the 32 x 32 -> 64-bit
-# integer multiply-add and the transcendental unit: log, sqrt, sin, cos, exp) take four.
+# in FP32 lane-slots of a direct implementation of the method's arithmetic (itemised in
+# the design doc).  An FP32 add / multiply / FMA / compare / select / integer op takes one slot; an
+# FP64 operation two (half rate); the 32 x 32 -> 64-bit integer multiply-add and the
+# transcendental unit (log, sqrt, sin, cos, exp) four (quarter rate).  The rates were measured
+# on the device with dependent-chain-free loops.
 #   noise      a Philox4x32-10 block serves 4 particles: 10 rounds x (2 multiply-adds x 4
-#              + 4 xors) / 4 = 30; half a Box-Muller pair: (9 full + 4 transcendental x 4)
-#              / 2 = 12.5                                                         -> 42.5
+#              + 4 xors) / 4 = 30; half a Box-Muller pair: (8 full + 4 transcendental x 4)
+#              / 2 = 12                                                           -> 42
 #   model      transition 2, log g 4, weight update and guard 3                   ->  9
-#   normalise  subtract and scale 2, exp 4, FP64 conversion and sums 3, normalised
-#              log-weight 1                                                       -> 10
-#   resample   per resampled step: FP64 prefix 2, offspring count 8 + two exact targets
-#              8 + compares 2, marker / max-scan 1, gather 1                       -> 22 r
-#   adjoint    transposed derivatives of log g and of the transition 13, scatter-add to
-#              the parent at a resampled step 2                                  -> 13 + 2 r
+#   normalise  FP64 running max 4, subtract / scale / exp 6, FP64 conversion and the two sums
+#              6, shifted carry 1                                                 -> 17
+#   resample   per resampled step: FP64 prefix 4, offspring count from P / tot 24, marker
+#              and gather 2                                                       -> 30 r
+#   adjoint    transposed derivatives of log g and of the transition 11, summed into the
+#              parameter adjoint 3, scatter-add to the parent at a resampled step 2 r
+#                                                                                 -> 14 + 2 r
 # Rebuilding the step in the adjoint (from checkpoints) is implementation work, not counted.
 def alg_slots_per_particle_step(M, r):
-    noise, model, normalise = 42.5, 9.0, 10.0
-    forward = noise + model + normalise + 22.0 * r
-    adjoint = 13.0 + 2.0 * r
+    noise, model, normalise = 42.0, 9.0, 17.0
+    forward = noise + model + normalise + 30.0 * r
+    adjoint = 14.0 + 2.0 * r
     return forward + adjoint
 
 
@@ -150,9 +153,12 @@ def cpu_baseline(w, seconds, threads):
                        "%.1f s wall" % (i, w.M, int(w.T_len[0]), w.name, dt))
 
 
-def measure(w, precision, steps, warmup, with_kernel=True, tune=True):
+def measure(w, precision, steps, warmup, with_kernel=True, tune=True, force=None):
     from paper_2407_17296_amd import autotune, driver
-    t = autotune.tune(w, precision) if tune else dict(tile=0, ckpt=0, store_noise=1)
+    if force is not None:
+        t = force
+    else:
+        t = autotune.tune(w, precision) if tune else dict(tile=0, ckpt=0, store_noise=0)
     run = driver.SMC2Run(w, precision=precision, tile=t["tile"], ckpt_interval=t["ckpt"],
                          store_noise=t.get("store_noise", 1))
     gpu_s, wall = _timed_graph(run, steps, warmup)
@@ -211,6 +217,11 @@ def main():
                          "reference for the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the library's default launch shapes instead of autotuning")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="force the launch shape of the mixed-precision main workload "
+                         "(with --ckpt and --store-noise; skips its tuning)")
+    ap.add_argument("--ckpt", type=int, default=0)
+    ap.add_argument("--store-noise", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the hot path shards by parameter sample and this build "
@@ -224,7 +235,9 @@ def main():
     print("[bench] workload %s S=%d N=%d M=%d T=%d, %d warmup + %d timed iterations" % (
         w.name, w.S, w.N, w.M, w.T_max, args.warmup, args.steps), file=sys.stderr, flush=True)
     tune = not args.no_tune
-    mixed = measure(w, smc2.MIXED, args.steps, args.warmup, tune=tune)
+    force = (dict(tile=args.tile, ckpt=args.ckpt, store_noise=args.store_noise)
+             if args.tile is not None else None)
+    mixed = measure(w, smc2.MIXED, args.steps, args.warmup, tune=tune, force=force)
     print("[bench] mixed: %.3f ms/iteration" % mixed["ms_per_step"], file=sys.stderr, flush=True)
 
     res = {}

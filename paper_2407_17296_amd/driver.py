@@ -38,7 +38,7 @@ class SMC2Run:
 
     def __init__(self, w, precision=smc2.MIXED, resampler=smc2.SYSTEMATIC, ess_frac=0.5,
                  ckpt_interval=0, tile=0, persistent=0, random_walk=0, gamma=None, device=0,
-                 seed=None, store_noise=1):
+                 seed=None, store_noise=0):
         self.w = w
         self.dev = torch.device("cuda", device)
         self.model = smc2.Model.from_workload(w)

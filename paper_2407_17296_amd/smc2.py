@@ -133,7 +133,7 @@ class Model:
 
 
 def pf_opts(precision=FP64, resampler=SYSTEMATIC, ess_frac=0.5, ckpt_interval=0, want_grad=1,
-            tile=0, persistent=0, store_noise=1):
+            tile=0, persistent=0, store_noise=0):
     return smc2_pf_opts(int(precision), int(resampler), float(ess_frac), int(ckpt_interval),
                         int(want_grad), int(tile), int(persistent), int(store_noise))
 
