@@ -583,6 +583,53 @@ double orc_lkernel_log_ratio(int32_t D, double gamma, const double *grad_prev,
   return -(npk - npp) / (2.0 * g2);
 }
 
+double orc_realised_estimate(int32_t N, int32_t D, const double *logw, const double *theta,
+                             double *mean, double *second) {
+  /* Realised estimates of the first two moments (eq. realised_estimates with f(theta) = theta
+   * and theta^2 elementwise) under the normalised weights of eq. normalise_smc2, and the
+   * iteration's recycling weight l_k = (sum_i w_i)^2 / sum_i w_i^2 (eq. recycling_I).  The
+   * weights are taken relative to their maximum, which cancels in every ratio.  Every weight
+   * zero: the moments are NaN and l_k = 0. */
+  double mx = kNegInf;
+  for (int i = 0; i < N; ++i) mx = std::max(mx, logw[i]);
+  if (mx == kNegInf) {
+    for (int p = 0; p < D; ++p) mean[p] = second[p] = std::nan("");
+    return 0.0;
+  }
+  double S = 0.0, Q = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double w = std::exp(logw[i] - mx);
+    S += w;
+    Q += w * w;
+  }
+  for (int p = 0; p < D; ++p) {
+    double m1 = 0.0, m2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double wn = std::exp(logw[i] - mx) / S; /* normalised weight */
+      double v = theta[(size_t)i * D + p];
+      m1 += wn * v;
+      m2 += wn * v * v;
+    }
+    mean[p] = m1;
+    second[p] = m2;
+  }
+  return S * S / Q;
+}
+
+void orc_recycle(int32_t K, int32_t D, const double *l, const double *est, double *out) {
+  /* Recycled estimate (Sec. III-C): sum_k c_k f_k with the optimal constants
+   * c_k = l_k / sum_k l_k (eq. opt_recycling_constant).  est is [K][D]; iterations with l_k = 0
+   * take no part. */
+  double L = 0.0;
+  for (int k = 0; k < K; ++k) L += l[k];
+  for (int p = 0; p < D; ++p) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k)
+      if (l[k] > 0.0) acc += (l[k] / L) * est[(size_t)k * D + p];
+    out[p] = acc;
+  }
+}
+
 int orc_smc2_run(const orc_model *mdl, const orc_pf_opts *pf, const orc_smc2_opts *so,
                  int32_t T, const double *y, double *rec_theta, double *rec_loglik,
                  double *rec_grad, double *rec_logw, double *rec_ess, int32_t *rec_resampled,

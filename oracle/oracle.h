@@ -102,6 +102,15 @@ void orc_langevin_move(int32_t D, double gamma, const double *theta, const doubl
 double orc_lkernel_log_ratio(int32_t D, double gamma, const double *grad_prev,
                              const double *grad_new, const double *p_prev);
 
+/* Realised estimates of E[theta] and E[theta^2] (elementwise) under the normalised weights of
+ * the sample population (eqs. realised_estimates, normalise_smc2); returns the recycling weight
+ * l_k = (sum w)^2 / sum w^2 (eq. recycling_I).  logw [N], theta [N][D], mean/second [D] out. */
+double orc_realised_estimate(int32_t N, int32_t D, const double *logw, const double *theta,
+                             double *mean, double *second);
+/* Recycled estimate sum_k c_k est_k with c_k = l_k / sum l (eq. opt_recycling_constant);
+ * l [K], est [K][D], out [D]. */
+void orc_recycle(int32_t K, int32_t D, const double *l, const double *est, double *out);
+
 /* A full SMC^2 run on one series (paper Sec. III with the CRN-PF of Sec. II).
  * Records, for k = 1..K (index k-1): proposed theta [K][N][D], loglik [K][N],
  * grad_loglik [K][N][D], log weights before resampling [K][N], ESS [K], resampled flag [K],

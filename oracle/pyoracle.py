@@ -86,6 +86,9 @@ def lib():
         L.orc_langevin_move.argtypes = [i32, ctypes.c_double, dp, dp, dp, dp, dp]
         L.orc_lkernel_log_ratio.argtypes = [i32, ctypes.c_double, dp, dp, dp]
         L.orc_lkernel_log_ratio.restype = ctypes.c_double
+        L.orc_realised_estimate.argtypes = [i32, i32, dp, dp, dp, dp]
+        L.orc_realised_estimate.restype = ctypes.c_double
+        L.orc_recycle.argtypes = [i32, i32, dp, dp, dp]
         L.orc_smc2_run.argtypes = [mp, op, ctypes.POINTER(_SMC2Opts), i32, dp, dp, dp, dp, dp, dp,
                                    ip, ip, dp, dp]
         L.orc_smc2_run.restype = ctypes.c_int
@@ -220,6 +223,24 @@ def langevin_move(gamma, theta, grad_logpost, xi):
 def lkernel_log_ratio(gamma, grad_prev, grad_new, p_prev):
     gp, gn, pp = _f64(grad_prev), _f64(grad_new), _f64(p_prev)
     return lib().orc_lkernel_log_ratio(len(gp), float(gamma), _dp(gp), _dp(gn), _dp(pp))
+
+
+def realised_estimate(logw, theta):
+    """(mean [D], second moment [D], recycling weight l) of a weighted sample population."""
+    logw, theta = _f64(logw), _f64(theta)
+    N, D = theta.shape
+    mean, second = np.zeros(D), np.zeros(D)
+    l = lib().orc_realised_estimate(N, D, _dp(logw), _dp(theta), _dp(mean), _dp(second))
+    return mean, second, l
+
+
+def recycle(l, est):
+    """Recycled estimate over iterations: l [K], est [K][D] -> [D]."""
+    l, est = _f64(l), _f64(est)
+    K, D = est.shape
+    out = np.zeros(D)
+    lib().orc_recycle(K, D, _dp(l), _dp(est), _dp(out))
+    return out
 
 
 def smc2_run(model, y, N, M, K, gamma, seed, series=0, resampler=SYSTEMATIC, ess_frac=0.5,

@@ -135,3 +135,54 @@ def test_smc2_reaches_the_posterior_mode(oracle):
     est = W @ rec["theta"][-1]
     assert logpost(est) > logpost(mode) - 1.5
     assert logpost(est) > logpost(np.zeros(w.D)) + 2.0  # better than the prior mean
+
+
+# ---- realised estimates and recycling (eqs. realised_estimates, recycling_I,
+#      opt_recycling_constant) ------------------------------------------------------------------
+
+def test_realised_estimate_special_cases(oracle):
+    """Equal weights give the sample mean and mean square with l = N; a single finite weight
+    gives that sample with l = 1; a constant added to every log-weight changes nothing; no
+    finite weight gives NaN moments and l = 0."""
+    rng = np.random.default_rng(3)
+    th = rng.standard_normal((40, 3))
+    m, s2, l = oracle.realised_estimate(np.zeros(40), th)
+    assert np.allclose(m, th.mean(0), rtol=1e-13) and np.allclose(s2, (th ** 2).mean(0), rtol=1e-13)
+    assert l == pytest.approx(40.0, rel=1e-13)
+    lw = np.full(40, -np.inf)
+    lw[7] = -3.0
+    m, s2, l = oracle.realised_estimate(lw, th)
+    assert np.array_equal(m, th[7]) and np.allclose(s2, th[7] ** 2) and l == 1.0
+    lw = rng.standard_normal(40) * 2
+    a = oracle.realised_estimate(lw, th)
+    b = oracle.realised_estimate(lw + 123.4, th)
+    assert np.allclose(a[0], b[0], rtol=1e-12) and np.allclose(a[1], b[1], rtol=1e-12)
+    assert a[2] == pytest.approx(b[2], rel=1e-12)
+    w = np.exp(lw - lw.max())
+    assert a[2] == pytest.approx(w.sum() ** 2 / (w * w).sum(), rel=1e-13)
+    m, s2, l = oracle.realised_estimate(np.full(40, -np.inf), th)
+    assert np.all(np.isnan(m)) and l == 0.0
+
+
+def test_realised_estimate_recovers_an_importance_sampling_target(oracle):
+    """Draws from N(0, 1) weighted by N(theta; 1.5, 0.7^2) / N(theta; 0, 1) estimate the mean and
+    second moment of N(1.5, 0.7^2): 1.5 and 1.5^2 + 0.49 (a sign or normalisation error in the
+    weighting shows up here)."""
+    rng = np.random.default_rng(4)
+    th = rng.standard_normal((200000, 1))
+    lw = stats.norm.logpdf(th[:, 0], 1.5, 0.7) - stats.norm.logpdf(th[:, 0])
+    m, s2, l = oracle.realised_estimate(lw, th)
+    assert abs(m[0] - 1.5) < 5.0 / np.sqrt(l)
+    assert abs(s2[0] - (1.5 ** 2 + 0.49)) < 20.0 / np.sqrt(l)
+    assert 0.1 * len(th) < l < len(th)
+
+
+def test_recycling_constants(oracle):
+    """c_k = l_k / sum l: equal l averages the estimates, one nonzero l selects its iteration,
+    K = 1 is the identity, and the result is the l-weighted mean."""
+    est = np.array([[1.0, -2.0], [3.0, 0.5], [-1.0, 4.0]])
+    assert np.allclose(oracle.recycle([2.0, 2.0, 2.0], est), est.mean(0), rtol=1e-14)
+    assert np.allclose(oracle.recycle([0.0, 5.0, 0.0], est), est[1], rtol=1e-14)
+    assert np.allclose(oracle.recycle([7.0], est[:1]), est[0], rtol=1e-14)
+    l = np.array([1.0, 3.0, 6.0])
+    assert np.allclose(oracle.recycle(l, est), (l[:, None] * est).sum(0) / l.sum(), rtol=1e-14)
