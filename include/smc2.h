@@ -196,6 +196,13 @@ typedef struct {
  *   p_prev : dev [S][N][D] from smc2_langevin_move (ignored if first_iteration).
  *   ancestors dev [S][N] int32 out (identity where not resampled), ess dev [S] FP64 out,
  *   resampled dev [S] int32 out; each may be NULL.
+ *   estimate dev [S][2][D] FP64 out (may be NULL): the realised estimates of E[theta] and
+ *   E[theta^2] (elementwise) under the normalised weights, before resampling (eq.
+ *   realised_estimates with eq. normalise_smc2); NaN for a series whose weights are all zero.
+ *   recycle dev [S][1 + 2D] FP64 in/out (may be NULL): running sums over iterations of
+ *   l_k = ESS_k (eq. recycling_I), l_k E[theta] and l_k E[theta^2]; the recycled estimate
+ *   (Sec. III-C, constants of eq. opt_recycling_constant) is recycle[s][1..] / recycle[s][0].
+ *   The caller zeroes it before the first iteration.
  * A series whose weights are all zero keeps its population and sets the device status word
  * to SMC2_E_NONFINITE (see smc2_ctx_device_status).
  * Errors: SMC2_E_INVALID_ARG for NULL pointers, N > 4096, sizes < 1, gamma <= 0. */
@@ -205,7 +212,7 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
                                    int32_t first_iteration, uint64_t seed,
                                    uint32_t *iteration, int32_t advance_iteration,
                                    int32_t *ancestors, double *ess, int32_t *resampled,
-                                   void *stream);
+                                   double *estimate, double *recycle, void *stream);
 
 /* ---- initialisation and inspection ------------------------------------------------------- */
 

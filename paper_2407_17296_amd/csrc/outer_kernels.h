@@ -57,6 +57,8 @@ struct OuterArgs {
   int32_t *anc_out;
   double *ess_out;
   int32_t *resampled_out;
+  double *estimate;  // [S][2][D] realised E[theta], E[theta^2] of this iteration, or NULL
+  double *recycle;   // [S][1 + 2D] running sums (l, l E[theta], l E[theta^2]), or NULL
   double *scratch;  // [S][N][2D+2] gather double buffer
   int32_t *status;
 };
@@ -72,6 +74,7 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
   constexpr double kNegInf = -__builtin_huge_val();
   __shared__ double sh_P[kOuterMaxN];
   __shared__ double sh_red[2][2 * WAVES + 2];
+  __shared__ double sh_est[WAVES][2 * kMaxD];
   const int s = blockIdx.x, tid = threadIdx.x;
   const int N = A.N, D = A.D;
   const int per = (N + kOuterThreads - 1) / kOuterThreads;
@@ -135,6 +138,37 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
   block_sum2<WAVES>(S, Q, sh_red[1]);
   const double ess = (mx == kNegInf) ? 0.0 : S * S / Q;  // eqs. normalise_smc2, ess_smc2
   const bool res = mx != kNegInf && ess < 0.5 * (double)N;
+  if (A.estimate || A.recycle) {
+    // realised estimates of E[theta] and E[theta^2] under the normalised weights (eq.
+    // realised_estimates) and the recycling weight l_k = ESS (eq. recycling_I), accumulated as
+    // l_k-weighted sums for the recycled estimate (eq. opt_recycling_constant)
+    const int lane = tid & 63, wid = tid >> 6;
+    for (int p = 0; p < D; ++p) {
+      double m1 = 0.0, m2 = 0.0;
+      for (int r = 0; r < per; ++r) {
+        const int i = i0 + r;
+        if (i >= N || !(e[r] > 0.0)) continue;  // zero-weight samples take no part
+        const double v = A.theta[((size_t)s * N + i) * D + p];
+        m1 += e[r] * v;
+        m2 += e[r] * v * v;
+      }
+      m1 = wave_sum(m1);
+      m2 = wave_sum(m2);
+      if (lane == 0) {
+        sh_est[wid][p] = m1;
+        sh_est[wid][D + p] = m2;
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * D) {
+      double v = 0.0;
+      for (int w = 0; w < WAVES; ++w) v += sh_est[w][tid];
+      v = (mx == kNegInf) ? __builtin_nan("") : v / S;
+      if (A.estimate) A.estimate[(size_t)s * 2 * D + tid] = v;
+      if (A.recycle && ess > 0.0) A.recycle[(size_t)s * (2 * D + 1) + 1 + tid] += ess * v;
+    }
+    if (tid == 0 && A.recycle) A.recycle[(size_t)s * (2 * D + 1)] += ess;
+  }
   if (tid == 0) {
     if (A.ess_out) A.ess_out[s] = ess;
     if (A.resampled_out) A.resampled_out[s] = res ? 1 : 0;

@@ -484,7 +484,7 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
                                    int32_t first_iteration, uint64_t seed,
                                    uint32_t *iteration, int32_t advance_iteration,
                                    int32_t *ancestors, double *ess, int32_t *resampled,
-                                   void *stream) {
+                                   double *estimate, double *recycle, void *stream) {
   if (!ctx || !ctx->reserved) return fail(SMC2_E_INVALID_ARG, "context not reserved");
   std::string why;
   if (!model_ok(model, why)) return fail(SMC2_E_INVALID_ARG, why);
@@ -523,6 +523,8 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
   a.anc_out = ancestors;
   a.ess_out = ess;
   a.resampled_out = resampled;
+  a.estimate = estimate;
+  a.recycle = recycle;
   a.scratch = ctx->outer_scratch;
   a.status = ctx->status;
   hipStream_t hs = (hipStream_t)stream;

@@ -27,6 +27,7 @@ class Records:
     resampled: np.ndarray  # [K][S]
     anc: np.ndarray        # [K][S][N]
     prev_theta: np.ndarray         # [K][S][N][D] population the move started from
+    estimate: np.ndarray   # [K][S][2][D] realised E[theta], E[theta^2] before resampling
     prev_logpost: np.ndarray       # [K][S][N]
     prev_grad_logpost: np.ndarray  # [K][S][N][D]
     prev_logw: np.ndarray          # [K][S][N]
@@ -62,6 +63,8 @@ class SMC2Run:
         self.iteration = torch.ones(1, dtype=torch.int32, device=self.dev)
         self.anc = torch.zeros((S, N), dtype=torch.int32, device=self.dev)
         self.ess = torch.zeros(S, **f64)
+        self.estimate = torch.zeros((S, 2, D), **f64)
+        self.recycle = torch.zeros((S, 1 + 2 * D), **f64)
         self.resampled = torch.zeros(S, dtype=torch.int32, device=self.dev)
         self._cur_c = smc2.population(**self.cur)
         self._prev_c = smc2.population(**self.prev)
@@ -80,7 +83,7 @@ class SMC2Run:
                                     None if first else self._prev_c,
                                     None if first else self.p_prev, int(first), self.seed,
                                     self.iteration, 1, self.anc, self.ess, self.resampled,
-                                    stream=stream)
+                                    self.estimate, self.recycle, stream=stream)
 
     def _move(self, stream=None):
         w = self.w
@@ -96,6 +99,7 @@ class SMC2Run:
         """k = 1: theta ~ prior, filter, weights = likelihood, normalise, ESS, resample."""
         w = self.w
         self.iteration.fill_(1)
+        self.recycle.zero_()
         smc2.smc2_prior_init(self.ctx.h, self.model, w.S, w.N, self.seed, self.cur["theta"])
         self._pf()
         self._reweight(first=True)
@@ -131,7 +135,14 @@ class SMC2Run:
         c = self.cur
         return dict(theta=c["theta"].cpu().numpy(), loglik=c["loglik"].cpu().numpy(),
                     logw=c["logw"].cpu().numpy(), ess=self.ess.cpu().numpy(),
-                    resampled=self.resampled.cpu().numpy(), anc=self.anc.cpu().numpy())
+                    resampled=self.resampled.cpu().numpy(), anc=self.anc.cpu().numpy(),
+                    estimate=self.estimate.cpu().numpy())
+
+    def recycled_estimate(self):
+        """Recycled E[theta], E[theta^2] over the iterations so far (Sec. III-C), [S][2][D]."""
+        r = self.recycle.cpu().numpy()
+        D = self.w.D
+        return (r[:, 1:] / r[:, :1]).reshape(-1, 2, D)
 
     def close(self):
         self.graph = None
@@ -182,6 +193,27 @@ def _iteration_recorded(run, k):
     run._carry()
     run.k = k
     return dict(theta=theta, loglik=loglik, grad=grad, logw=snap["logw"], ess=snap["ess"],
-                resampled=snap["resampled"], anc=snap["anc"], prev_theta=prev["theta"],
+                resampled=snap["resampled"], anc=snap["anc"], estimate=snap["estimate"],
+                prev_theta=prev["theta"],
                 prev_logpost=prev["logpost"], prev_grad_logpost=prev["grad_logpost"],
                 prev_logw=prev["logw"], p_prev=p_prev)
+
+
+def pilot_gamma(w, candidates=(0.01, 0.02, 0.04, 0.085, 0.175), K=10, random_walk=0, **kw):
+    """Step-size pilot as the paper chose its step sizes (Sec. IV-A: several runs over a range
+    of step sizes, the best kept): a K-iteration run per candidate, scored by the mean ESS over
+    the iterations (the data-generating parameters are unknown in use).  Returns
+    (best gamma, {gamma: mean ESS / N})."""
+    scores = {}
+    for g in candidates:
+        run, rec = run_smc2(w, K=K, random_walk=random_walk, gamma=g, **kw)
+        run.close()
+        scores[float(g)] = float(np.mean(rec.ess)) / w.N
+    best = max(scores, key=scores.get)
+    return best, scores
+
+
+def mse_per_iteration(rec, theta_true, s=0):
+    """Squared error of each iteration's realised E[theta] against reference parameters,
+    averaged over the D components ([K])."""
+    return np.mean((rec.estimate[:, s, 0, :] - np.asarray(theta_true)) ** 2, axis=1)

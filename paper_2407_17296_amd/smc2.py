@@ -68,7 +68,8 @@ SIGNATURES = [
     ("smc2_langevin_move", ctypes.c_int, [_VP, _MP, _I32, _I32, _D, _I32, _VP, _VP, _U64, _VP,
                                           _VP, _VP, _VP]),
     ("smc2_reweight_resample", ctypes.c_int, [_VP, _MP, _I32, _I32, _D, _I32, _POP, _POP, _VP,
-                                              _I32, _U64, _VP, _I32, _VP, _VP, _VP, _VP]),
+                                              _I32, _U64, _VP, _I32, _VP, _VP, _VP, _VP, _VP,
+                                              _VP]),
     ("smc2_prior_init", ctypes.c_int, [_VP, _MP, _I32, _I32, _U64, _VP, _VP]),
     ("smc2_pf_trace", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP, _VP]),
     ("smc2_philox_probe", ctypes.c_int, [_I32, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -203,14 +204,16 @@ def population(theta, logpost, grad_logpost, loglik, logw):
 
 def smc2_reweight_resample(ctx, model, S, N, gamma, random_walk, cur, prev, p_prev,
                            first_iteration, seed, iteration, advance_iteration=0,
-                           ancestors=None, ess=None, resampled=None, stream=None):
+                           ancestors=None, ess=None, resampled=None, estimate=None,
+                           recycle=None, stream=None):
     _check(lib().smc2_reweight_resample(
         ctx, ctypes.byref(model.c), int(S), int(N), float(gamma), int(random_walk),
         ctypes.byref(cur), None if prev is None else ctypes.byref(prev),
         _ptr(p_prev, torch.float64, "p_prev"), int(first_iteration), int(seed),
         _ptr(iteration, torch.int32, "iteration"), int(advance_iteration),
         _ptr(ancestors, torch.int32, "ancestors"), _ptr(ess, torch.float64, "ess"),
-        _ptr(resampled, torch.int32, "resampled"), _stream(stream)), "smc2_reweight_resample")
+        _ptr(resampled, torch.int32, "resampled"), _ptr(estimate, torch.float64, "estimate"),
+        _ptr(recycle, torch.float64, "recycle"), _stream(stream)), "smc2_reweight_resample")
 
 
 def smc2_prior_init(ctx, model, S, N, seed, theta, stream=None):

@@ -73,6 +73,11 @@ def _check_iteration(oracle, w, rec, k, s=0, pf_items=8):
     else:
         assert np.array_equal(rec.anc[k, s], np.arange(N)), k
         assert np.allclose(rec.logw[k, s], logw, rtol=1e-13, atol=1e-13), k
+    # realised estimates before resampling (eq. realised_estimates)
+    m1, m2, l = oracle.realised_estimate(logw, th)
+    assert np.allclose(rec.estimate[k, s, 0], m1, rtol=1e-12, atol=1e-14), k
+    assert np.allclose(rec.estimate[k, s, 1], m2, rtol=1e-12, atol=1e-14), k
+    assert l == pytest.approx(rec.ess[k, s], rel=1e-12), k
     return res
 
 
@@ -84,8 +89,13 @@ def test_fp64_smc2_iterations_match_oracle(oracle, index, kw, K):
     w.prior_mu, w.prior_sd = (np.array(v, dtype=float) for v in PRIORS[index])
     say("  smc2 %s N=%d M=%d K=%d" % (w.name, w.N, w.M, K))
     run, rec = driver.run_smc2(w, K=K, precision=smc2.FP64)
+    recycled = run.recycled_estimate()
     run.close()
     resampled = [k + 1 for k in range(K) if _check_iteration(oracle, w, rec, k)]
+    # recycled estimate over the iterations (Sec. III-C) from the per-iteration l_k and moments
+    for j in range(2):
+        want = oracle.recycle(rec.ess[:, 0], rec.estimate[:, 0, j, :])
+        assert np.allclose(recycled[0, j], want, rtol=1e-12, atol=1e-14), j
     o = _oracle_run(oracle, w, K)
     drift = max(np.max(np.abs(rec.theta[k, 0] - o["theta"][k])) for k in range(K))
     assert drift < 1e-6
@@ -143,3 +153,31 @@ def test_all_zero_weights_set_the_device_status():
     assert smc2.smc2_ctx_device_status(run.ctx.h) == smc2.SMC2_E_NONFINITE
     assert np.all(run.ess.cpu().numpy() == 0.0)
     run.close()
+
+
+def test_first_order_and_random_walk_proposals():
+    """The shape of the paper's Tables II and III on the synthetic 1-D LG workload: the
+    recycled estimate's squared error against the data-generating parameters and the mean ESS
+    of the Langevin proposal (SMC1, step 0.085) and of the random walk (SMC0, step 0.175).
+    Reported, not asserted beyond sanity: the comparison is a Monte Carlo quantity."""
+    w = synth.make(1, N=256, M=256)
+    out = {}
+    for name, rw, gamma in (("SMC1", 0, 0.085), ("SMC0", 1, 0.175)):
+        run, rec = driver.run_smc2(w, K=20, precision=smc2.MIXED, random_walk=rw, gamma=gamma)
+        est = run.recycled_estimate()[0, 0]
+        run.close()
+        mse = float(np.mean((est - w.theta_true) ** 2))
+        ess = float(np.mean(rec.ess[:, 0])) / w.N
+        out[name] = (mse, ess)
+        say("  %s: recycled E[theta] %s, MSE %.3g, mean ESS / N %.3f" % (
+            name, np.array2string(est, precision=3), mse, ess))
+        assert np.all(np.isfinite(est)) and 0.0 < ess <= 1.0
+
+
+def test_step_size_pilot_picks_the_best_mean_ess():
+    w = synth.make(0, N=32)
+    best, scores = driver.pilot_gamma(w, candidates=(0.02, 0.085, 0.175), K=4,
+                                      precision=smc2.FP64)
+    say("  pilot mean ESS / N: %s -> gamma %.3f" % (scores, best))
+    assert best in scores and scores[best] == max(scores.values())
+    assert all(0.0 < v <= 1.0 for v in scores.values())
