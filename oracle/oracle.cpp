@@ -130,8 +130,13 @@ inline double re(const cplx &v) { return v.real(); }
  *                                     y = x^2/20 + sy w,  x_0 ~ N(0,1)   (C17, C18)
  *   SV      (mu, atanh phi, log s):   x_t = mu + phi (x - mu) + s e,  y = exp(x/2) w,
  *                                     x_0 ~ N(mu, s^2/(1-phi^2))         (C16, C17)
+ *   LG1D_OPT (a, log sx, log sy): the LG1D model filtered with the "optimal" proposal of
+ *                                     Sec. IV-A, q(x_t | x_{t-1}, y_t) = N(rho^2 (y/sy^2 +
+ *                                     a x_{t-1}/sx^2), rho^2), 1/rho^2 = 1/sx^2 + 1/sy^2, and
+ *                                     incremental weight p(y_t | x_{t-1}) =
+ *                                     N(y_t; a x_{t-1}, sx^2 + sy^2) (C24)
  * The bootstrap proposal q = f is written in reparameterised form x = mu(x) + sqrt(C) e
- * (eq. reparam_epsilon).  Each routine also returns the partial derivatives that the tangent
+ * (eq. reparam_epsilon), and the optimal proposal likewise x = m(x, y) + rho e.  Each routine also returns the partial derivatives that the tangent
  * recursion of eqs. df..dxk needs; they are only used by the real instantiation. */
 
 template <class R>
@@ -219,6 +224,45 @@ struct Model {
     }
   }
 
+  /* The optimal proposal of the LG1D_OPT model: x_t = m(x_{t-1}, y_t) + rho e_t with
+   * m = rho^2 (y / sy^2 + a x / sx^2); tangent dx_new = m_x dx_old + m_theta + rho_theta e
+   * (eq. dxk for this proposal). */
+  void propagate_opt(R *x, const double *e, const double *y, double *dx) const {
+    R a = th[0], isx2 = std::exp(-2.0 * th[1]), isy2 = std::exp(-2.0 * th[2]);
+    R rho2 = 1.0 / (isx2 + isy2), rho = std::sqrt(rho2);
+    R xo = x[0];
+    R m = rho2 * (y[0] * isy2 + a * xo * isx2);
+    x[0] = m + rho * e[0];
+    if (dx) {
+      double ar = re(a), xr = re(xo), r2 = re(rho2), r1 = re(rho), ix = re(isx2), iy = re(isy2);
+      double mr = re(m);
+      double mx = r2 * ar * ix;                                  /* d m / d x_{t-1} */
+      double ma = r2 * xr * ix;                                  /* d m / d a */
+      /* d rho^2 / d log sx = 2 rho^4 / sx^2, so d m / d log sx = 2 rho^2 / sx^2 (m - a x) and
+       * d rho / d log sx = rho^3 / sx^2; likewise for log sy with y in place of a x */
+      double mu = 2.0 * r2 * ix * (mr - ar * xr) + r1 * r2 * ix * e[0];
+      double mv = 2.0 * r2 * iy * (mr - y[0]) + r1 * r2 * iy * e[0];
+      dx[0] = mx * dx[0] + ma;
+      dx[1] = mx * dx[1] + mu;
+      dx[2] = mx * dx[2] + mv;
+    }
+  }
+
+  /* Incremental weight of the optimal proposal, log N(y_t; a x_{t-1}, sx^2 + sy^2), from the
+   * state BEFORE the step; partial derivatives dl_dx [1] (w.r.t. x_{t-1}) and dl_dth [3]. */
+  R logp_pred(const double *y, const R *x, double *dl_dx, double *dl_dth) const {
+    R a = th[0], vx = std::exp(2.0 * th[1]), vy = std::exp(2.0 * th[2]);
+    R s2 = vx + vy, r = y[0] - a * x[0];
+    if (dl_dx) {
+      double rr = re(r), is2 = 1.0 / re(s2), q = rr * rr * is2 - 1.0;
+      dl_dx[0] = re(a) * rr * is2;
+      dl_dth[0] = re(x[0]) * rr * is2;
+      dl_dth[1] = re(vx) * is2 * q;
+      dl_dth[2] = re(vy) * is2 * q;
+    }
+    return -kHalfLog2Pi - 0.5 * std::log(s2) - 0.5 * r * r / s2;
+  }
+
   /* lambda = log g(y_t | x_t, theta).  With dl_dx [d] and dl_dth [D] (eq. deriv_loglike). */
   R logg(const double *y, const R *x, double *dl_dx, double *dl_dth) const {
     switch (kind) {
@@ -275,6 +319,7 @@ bool model_ok(const orc_model *m) {
     case ORC_LG_DIAG: return m->d >= 1 && m->D == m->d + 2;
     case ORC_GROWTH: return m->d == 1 && m->D == 2;
     case ORC_SV: return m->d == 1 && m->D == 3;
+    case ORC_LG1D_OPT: return m->d == 1 && m->D == 3;
   }
   return false;
 }
@@ -358,20 +403,32 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
       for (int q = 0; q < d; ++q)
         eps[q] = filter_normal(seed, fid, c3_step, (uint32_t)t, (uint32_t)(j * d + q));
       double *dxj = tangent ? &dx[(size_t)j * d * D] : nullptr;
-      mod.propagate(t, &x[(size_t)j * d], eps.data(), dxj);
-      R lam = mod.logg(yt, &x[(size_t)j * d], tangent ? dl_dx.data() : nullptr,
+      R lam;
+      if (mdl->kind == ORC_LG1D_OPT) {
+        /* optimal proposal: the weight p(y_t | x_{t-1}) uses the state before the step, so it
+         * and its tangent are taken first, then the particle moves */
+        lam = mod.logp_pred(yt, &x[(size_t)j * d], tangent ? dl_dx.data() : nullptr,
+                            tangent ? dl_dth.data() : nullptr);
+        if (tangent)
+          for (int p = 0; p < D; ++p)
+            lwd[(size_t)j * D + p] = gam[(size_t)j * D + p] + dl_dth[p] + dl_dx[0] * dxj[p];
+        mod.propagate_opt(&x[(size_t)j * d], eps.data(), yt, dxj);
+      } else {
+        mod.propagate(t, &x[(size_t)j * d], eps.data(), dxj);
+        lam = mod.logg(yt, &x[(size_t)j * d], tangent ? dl_dx.data() : nullptr,
                        tangent ? dl_dth.data() : nullptr);
-      if (std::isnan(re(lam))) lam = R(kNegInf);
-      lw[j] = lW[j] + lam;
-      if (tangent) {
-        /* d log w_t = d log w_{t-1} + dL/dtheta, dL = dL/dx dx/dtheta + dL/dtheta (eqs.
-         * weightupdate, deriv_loglike) */
-        for (int p = 0; p < D; ++p) {
-          double v = gam[(size_t)j * D + p] + dl_dth[p];
-          for (int q = 0; q < d; ++q) v += dl_dx[q] * dxj[q * D + p];
-          lwd[(size_t)j * D + p] = v;
+        if (tangent) {
+          /* d log w_t = d log w_{t-1} + dL/dtheta, dL = dL/dx dx/dtheta + dL/dtheta (eqs.
+           * weightupdate, deriv_loglike) */
+          for (int p = 0; p < D; ++p) {
+            double v = gam[(size_t)j * D + p] + dl_dth[p];
+            for (int q = 0; q < d; ++q) v += dl_dx[q] * dxj[q * D + p];
+            lwd[(size_t)j * D + p] = v;
+          }
         }
       }
+      if (std::isnan(re(lam))) lam = R(kNegInf);
+      lw[j] = lW[j] + lam;
     }
     /* log normaliser s_t = log sum_j exp(lw_j) (eq. likelihood_pf_ accumulated step-wise, C1) */
     double mx = kNegInf;
@@ -446,8 +503,8 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
 template <class R>
 R kalman_ll(const orc_model *mdl, const R *th, int T, const double *y) {
   const int d = mdl->d;
-  R lsx = (mdl->kind == ORC_LG1D) ? th[1] : th[d];
-  R lsy = (mdl->kind == ORC_LG1D) ? th[2] : th[d + 1];
+  R lsx = (mdl->kind == ORC_LG_DIAG) ? th[d] : th[1];
+  R lsy = (mdl->kind == ORC_LG_DIAG) ? th[d + 1] : th[2];
   R qv = std::exp(2.0 * lsx), rv = std::exp(2.0 * lsy);
   R ll = R(0.0);
   for (int q = 0; q < d; ++q) { /* LG_DIAG factorises into d independent scalar filters */
@@ -533,7 +590,8 @@ int orc_pf_complex_step(const orc_model *mdl, const orc_pf_opts *opt, const doub
 
 int orc_kalman(const orc_model *mdl, const double *theta, int32_t T, const double *y,
                double *loglik, double *grad) {
-  if (!model_ok(mdl) || (mdl->kind != ORC_LG1D && mdl->kind != ORC_LG_DIAG) || !theta ||
+  if (!model_ok(mdl) ||
+      (mdl->kind != ORC_LG1D && mdl->kind != ORC_LG_DIAG && mdl->kind != ORC_LG1D_OPT) || !theta ||
       !loglik || T < 0)
     return 1;
   *loglik = kalman_ll<double>(mdl, theta, T, y);

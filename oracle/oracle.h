@@ -30,7 +30,7 @@ extern "C" {
 #endif
 
 /* model kinds (same numbering as the library's smc2_model_kind, written out again here) */
-enum { ORC_LG1D = 0, ORC_LG_DIAG = 1, ORC_GROWTH = 2, ORC_SV = 3 };
+enum { ORC_LG1D = 0, ORC_LG_DIAG = 1, ORC_GROWTH = 2, ORC_SV = 3, ORC_LG1D_OPT = 4 };
 /* random streams of the counter contract */
 enum { ORC_INIT_NORMAL = 1, ORC_STEP_NORMAL = 2, ORC_RESAMPLE_UNIFORM = 3, ORC_PRIOR_NORMAL = 4,
        ORC_MOVE_NORMAL = 5, ORC_OUTER_RESAMPLE_UNIFORM = 6 };
@@ -88,7 +88,7 @@ int orc_pf_complex_step(const orc_model *mdl, const orc_pf_opts *opt, const doub
                         int32_t *ancestors);
 
 /* Exact log-likelihood of the linear-Gaussian models by the Kalman filter, and its gradient by
- * complex step (ORC_LG1D, ORC_LG_DIAG only). */
+ * complex step (ORC_LG1D, ORC_LG_DIAG, ORC_LG1D_OPT). */
 int orc_kalman(const orc_model *mdl, const double *theta, int32_t T, const double *y,
                double *loglik, double *grad);
 

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.cpp")
 
-LG1D, LG_DIAG, GROWTH, SV = 0, 1, 2, 3
+LG1D, LG_DIAG, GROWTH, SV, LG1D_OPT = 0, 1, 2, 3, 4
 INIT_NORMAL, STEP_NORMAL, RESAMPLE_UNIFORM, PRIOR_NORMAL, MOVE_NORMAL, OUTER_RESAMPLE_UNIFORM = (
     1, 2, 3, 4, 5, 6)
 SYSTEMATIC, MULTINOMIAL = 0, 1
