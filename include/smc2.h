@@ -62,12 +62,17 @@ typedef enum {
  *   SMC2_MODEL_SV      d=1,  D=3:  theta = (mu, atanh phi, log s);
  *                      x_t = mu + phi (x_{t-1} - mu) + s v, y_t = exp(x_t/2) w,
  *                      x_0 ~ N(mu, s^2/(1-phi^2))
+ *   SMC2_MODEL_LG1D_OPT d=1, D=3:  the LG1D model filtered with the "optimal" proposal of
+ *                      Sec. IV-A instead of the bootstrap one: x_t ~ N(rho^2 (y_t/sy^2 +
+ *                      a x_{t-1}/sx^2), rho^2) with 1/rho^2 = 1/sx^2 + 1/sy^2, weighted by the
+ *                      predictive density N(y_t; a x_{t-1}, sx^2 + sy^2)
  * with v, w ~ N(0, 1).  The prior p(theta) is independent N(prior_mu[p], prior_sd[p]^2). */
 typedef enum {
   SMC2_MODEL_LG1D = 0,
   SMC2_MODEL_LG_DIAG = 1,
   SMC2_MODEL_GROWTH = 2,
-  SMC2_MODEL_SV = 3
+  SMC2_MODEL_SV = 3,
+  SMC2_MODEL_LG1D_OPT = 4
 } smc2_model_kind;
 
 typedef struct {

@@ -1,8 +1,11 @@
 // The state-space models of the library (paper eqs. xt and yt), each with the pieces the fused
-// filter kernel needs: the initial draw, the reparameterised bootstrap transition
-// x_t = mu(x_{t-1}, theta) + sqrt(C(theta)) e_t (eq. reparam_epsilon), the observation
-// log-density lambda = log g(y_t | x_t, theta), and the transposed (adjoint) forms of their
-// derivatives (App. A, eqs. deriv_loglike and df..dxk, transposed).
+// filter kernel needs: the initial draw and one filter step, `advance`, which moves a particle
+// with its reparameterised noise (eq. reparam_epsilon) and returns the log incremental weight,
+// and the transposed (adjoint) form of its derivatives, `advance_adj` (App. A, eqs.
+// deriv_loglike and df..dxk, transposed).  With the bootstrap proposal (Sec. II) a step is the
+// transition x_t = mu(x_{t-1}, theta) + sqrt(C(theta)) e_t followed by the observation
+// log-density log g(y_t | x_t, theta); the optimal proposal of the 1-D LG model (Sec. IV-A)
+// moves by q(x_t | x_{t-1}, y_t) and weighs by p(y_t | x_{t-1}).
 //
 // R is the arithmetic type of propagation and weighting (double in the plain FP64 form, float
 // in the mixed form).  Parameters arrive in FP64 and are transformed once in FP64.  Gradient
@@ -31,9 +34,29 @@ __device__ __forceinline__ double fmar(double a, double b, double c) {
   return __builtin_fma(a, b, c);
 }
 
+// A bootstrap step from a model's transition (step / step_adj) and observation density
+// (logg / logg_adj): advance = step then log g at the new state.
+template <class Derived, typename R>
+struct Bootstrap {
+  __device__ R advance(R *x, const R *e, const R *y) const {
+    const Derived &m = *static_cast<const Derived *>(this);
+    m.step(x, e);
+    return m.logg(y, x);
+  }
+  // xb: adjoint of the state after the step on entry, before it on return; wb: adjoint of
+  // the step's log-weight; xp / xn: the state before / after the step
+  template <typename Acc>
+  __device__ void advance_adj(const R *y, const R *xp, const R *xn, const R *e, R wb, R *xb,
+                              Acc *tb) const {
+    const Derived &m = *static_cast<const Derived *>(this);
+    m.logg_adj(y, xn, wb, xb, tb);
+    m.step_adj(xp, e, xb, tb);
+  }
+};
+
 // x_t = a x + sx e;  y = x + sy w;  theta = (a, log sx, log sy);  x_0 ~ N(0, 1).
 template <typename R>
-struct ModelLG1D {
+struct ModelLG1D : Bootstrap<ModelLG1D<R>, R> {
   static constexpr int DX = 1, NP = 3;
   R a, sx, c0, isy;  // c0 = -log(2 pi)/2 - log sy
   __device__ void setup(const double *th) {
@@ -69,7 +92,7 @@ struct ModelLG1D {
 // x_t,q = A_q x_q + sx e_q;  y_q = x_q + sy w_q;  theta = (A_1..A_d, log sx, log sy);
 // x_0 ~ N(0, I).  A is diagonal, so the transition is elementwise.
 template <typename R, int D_X>
-struct ModelLGDiag {
+struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
   static constexpr int DX = D_X, NP = D_X + 2;
   R A[D_X], sx, c0, isy;  // c0 = d (-log(2 pi)/2 - log sy)
   __device__ void setup(const double *th) {
@@ -125,7 +148,7 @@ struct ModelLGDiag {
 // x_t = x/2 + 25 x/(1+x^2) + 8 cos(1.2 t) + sx e;  y = x^2/20 + sy w;
 // theta = (log sx, log sy);  x_0 ~ N(0, 1).
 template <typename R>
-struct ModelGrowth {
+struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
   static constexpr int DX = 1, NP = 2;
   R sx, c0, isy, drive;  // c0 = -log(2 pi)/2 - log sy
   __device__ void setup(const double *th) {
@@ -164,7 +187,7 @@ struct ModelGrowth {
 // x_t = mu + phi (x - mu) + s e;  y = exp(x/2) w;  theta = (mu, atanh phi, log s);
 // x_0 ~ N(mu, s^2 / (1 - phi^2)) = mu + s cosh(theta_1) e_0.
 template <typename R>
-struct ModelSV {
+struct ModelSV : Bootstrap<ModelSV<R>, R> {
   static constexpr int DX = 1, NP = 3;
   R mu, phi, s, sd0, dsd0;  // dsd0 = d sd0 / d theta_1 = s sinh(theta_1)
   __device__ void setup(const double *th) {
@@ -197,6 +220,56 @@ struct ModelSV {
   template <typename Acc>
   __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, Acc *) const {
     xb[0] += mulz(wb, fmar((R)0.5 * y[0] * y[0], fexp(-x[0]), (R)-0.5));
+  }
+};
+
+// The 1-D LG model filtered with the optimal proposal of Sec. IV-A:
+//   x_t = m + rho e,  m = rho^2 (y_t / sy^2 + a x_{t-1} / sx^2),  1/rho^2 = 1/sx^2 + 1/sy^2,
+// weighted by the predictive density log N(y_t; a x_{t-1}, sx^2 + sy^2) of the state before the
+// step.  theta = (a, log sx, log sy); x_0 ~ N(0, 1).
+template <typename R>
+struct ModelLG1DOpt {
+  static constexpr int DX = 1, NP = 3;
+  // kx = dm/dx = rho^2 a / sx^2, ky = rho^2 / sy^2, rx = rho^2 / sx^2, c0 = -log(2 pi)/2 -
+  // log(s2)/2 and is2 = 1/s2 with s2 = sx^2 + sy^2, fx / fy = sx^2 / s2, sy^2 / s2
+  R a, kx, ky, rx, rho, c0, is2, fx, fy;
+  __device__ void setup(const double *th) {
+    const double vx = exp(2.0 * th[1]), vy = exp(2.0 * th[2]);
+    const double rho2 = 1.0 / (1.0 / vx + 1.0 / vy), s2 = vx + vy;
+    a = (R)th[0];
+    kx = (R)(rho2 * th[0] / vx);
+    ky = (R)(rho2 / vy);
+    rx = (R)(rho2 / vx);
+    rho = (R)sqrt(rho2);
+    c0 = (R)(-kHalfLog2Pi - 0.5 * log(s2));
+    is2 = (R)(1.0 / s2);
+    fx = (R)(vx / s2);
+    fy = (R)(vy / s2);
+  }
+  __device__ void per_step(int) {}
+  __device__ void init(const R *e0, R *x) const { x[0] = e0[0]; }
+  __device__ void init_adj(const R *, const R *, double *) const {}
+  __device__ R advance(R *x, const R *e, const R *y) const {
+    const R xo = x[0], r = fmar(-a, xo, y[0]);
+    x[0] = fmar(ky, y[0], fmar(kx, xo, rho * e[0]));
+    return fmar((R)-0.5 * r * is2, r, c0);
+  }
+  template <typename Acc>
+  __device__ void advance_adj(const R *y, const R *xp, const R *xn, const R *e, R wb, R *xb,
+                              Acc *tb) const {
+    const R x = xp[0], r = fmar(-a, x, y[0]), q = fmar(r * is2, r, (R)-1);
+    const R m = fmar(-rho, e[0], xn[0]);  // the proposal mean
+    const R g = xb[0];
+    // the weight's dependence on theta and on x_{t-1}
+    tb[0] += (Acc)mulz(wb, x * r * is2);
+    tb[1] += (Acc)mulz(wb, fx * q);
+    tb[2] += (Acc)mulz(wb, fy * q);
+    // the new state's: dm/da = rho^2 x / sx^2; d x_t / d log sx = rho^2 / sx^2 (2 (m - a x) +
+    // rho e); d x_t / d log sy = rho^2 / sy^2 (2 (m - y) + rho e)
+    tb[0] += (Acc)mulz(g, rx * x);
+    tb[1] += (Acc)mulz(g, rx * fmar((R)2, m - a * x, rho * e[0]));
+    tb[2] += (Acc)mulz(g, ky * fmar((R)2, m - y[0], rho * e[0]));
+    xb[0] = fmar(kx, g, mulz(wb, a * r * is2));
   }
 };
 

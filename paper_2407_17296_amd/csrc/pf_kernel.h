@@ -341,8 +341,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         if (nz) store_noise(t, e);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          mdl.step(x[p], e[p]);
-          R v = lW[p] + mdl.logg(yv, x[p]);  // lW now holds the unnormalised lw
+          R v = lW[p] + mdl.advance(x[p], e[p], yv);  // lW now holds the unnormalised lw
           if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
           lW[p] = v;
           mloc = fmax(mloc, (double)v);
@@ -537,8 +536,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       for (int k = 0; k < NP; ++k) tp[k] = (R)0;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        mdl.logg_adj(yv, xn[p], wb[p], xb[p], tp);
-        mdl.step_adj(xp[p], ce[p], xb[p], tp);
+        mdl.advance_adj(yv, xp[p], xn[p], ce[p], wb[p], xb[p], tp);
       }
 #pragma unroll
       for (int k = 0; k < NP; ++k) tb[k] += (double)tp[k];
@@ -598,10 +596,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
         for (int p = 0; p < PPL; ++p) {
 #pragma unroll
           for (int q = 0; q < DX; ++q) xn[p][q] = cx[p][q];
-          mdl.step(xn[p], ce[p]);
+          const R lam = mdl.advance(xn[p], ce[p], yv);
           cw[p] = (R)0;
           if (need_w) {
-            R v = cl[p] + mdl.logg(yv, xn[p]);
+            R v = cl[p] + lam;
             if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
             cw[p] = fexp(v - st);
           }
@@ -655,8 +653,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
               row[q * LD + j0 + p] = x[p][q];
               if (!nz) row[(DX + q) * LD + j0 + p] = e[p][q];
             }
-            mdl.step(x[p], e[p]);
-            R v = lW[p] + mdl.logg(yv, x[p]);
+            R v = lW[p] + mdl.advance(x[p], e[p], yv);
             if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
             wv[p] = v;
             lW[p] = v - mt;
@@ -716,11 +713,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
           if (t - 1 > t0) load_step(t - 1);
           mdl.per_step(t);
+          const R *yv = sh_y + (size_t)(t - 1) * DX;
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
 #pragma unroll
             for (int q = 0; q < DX; ++q) xn[p][q] = cx[p][q];
-            mdl.step(xn[p], ce[p]);
+            (void)mdl.advance(xn[p], ce[p], yv);
           }
           reverse_step(t, cx, xn, ce, cw, ca);
         }

@@ -91,5 +91,6 @@ void register_lg1d(std::vector<PFKernel> &);
 void register_growth(std::vector<PFKernel> &);
 void register_sv(std::vector<PFKernel> &);
 void register_lgdiag(std::vector<PFKernel> &);
+void register_lg1dopt(std::vector<PFKernel> &);
 
 }  // namespace smc2

@@ -40,6 +40,7 @@ const std::vector<PFKernel> &kernels() {
     register_growth(v);
     register_sv(v);
     register_lgdiag(v);
+    register_lg1dopt(v);
   });
   return v;
 }
@@ -66,6 +67,9 @@ bool model_ok(const smc2_model *m, std::string &why) {
       break;
     case SMC2_MODEL_SV:
       if (m->d_x != 1 || m->D != 3) return why = "SV needs d_x = 1, D = 3", false;
+      break;
+    case SMC2_MODEL_LG1D_OPT:
+      if (m->d_x != 1 || m->D != 3) return why = "LG1D_OPT needs d_x = 1, D = 3", false;
       break;
     default:
       return why = "unknown model kind", false;

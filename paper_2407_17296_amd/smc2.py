@@ -18,7 +18,7 @@ SMC2_OK, SMC2_E_INVALID_ARG, SMC2_E_UNSUPPORTED, SMC2_E_OUT_OF_MEMORY, SMC2_E_DE
     SMC2_E_NONFINITE = range(6)
 STATUS_NAMES = {0: "SMC2_OK", 1: "SMC2_E_INVALID_ARG", 2: "SMC2_E_UNSUPPORTED",
                 3: "SMC2_E_OUT_OF_MEMORY", 4: "SMC2_E_DEVICE", 5: "SMC2_E_NONFINITE"}
-LG1D, LG_DIAG, GROWTH, SV = 0, 1, 2, 3
+LG1D, LG_DIAG, GROWTH, SV, LG1D_OPT = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 SYSTEMATIC, MULTINOMIAL = 0, 1
 

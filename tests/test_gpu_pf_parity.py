@@ -294,3 +294,58 @@ def test_lg1d_estimates_sit_at_the_kalman_value():
         sd = l.std()
         say("  precision %d: mean loglik %.4f, Kalman %.4f, sd %.3f" % (prec, l.mean(), lkf, sd))
         assert abs(l.mean() - lkf) < 0.5 * sd * sd + 4 * sd / np.sqrt(w.N) + 0.05
+
+
+# ----------------------------------------------- the optimal proposal of Sec. IV-A ----
+
+def _opt(w):
+    """The same data, filtered with the LG model's optimal proposal."""
+    w.kind = smc2.LG1D_OPT
+    w.name = w.name + "_opt"
+    return w
+
+
+@pytest.mark.parametrize("resampler", [smc2.SYSTEMATIC, smc2.MULTINOMIAL])
+def test_fp64_optimal_proposal_small(oracle, resampler):
+    w = _opt(synth.make(0))
+    theta = synth.prior_draws(w)
+    items = [(0, i) for i in range(w.N)]
+    ll, g, tr = gpu_pf(w, theta, resampler=resampler, k=2, ess_frac=0.9, trace_items=items)
+    _check_fp64(oracle, w, theta, ll, g, tr, k=2, resampler=resampler, ess_frac=0.9)
+
+
+@pytest.mark.parametrize("ckpt", [0, 1])
+def test_fp64_optimal_proposal_full_size_sampled(oracle, ckpt):
+    w = _opt(synth.make(1))
+    theta = spread_theta(w, 0.3, seed=12)
+    sample = [(0, i) for i in (0, 3, 300, 700, 1023)]
+    ll, g, tr = gpu_pf(w, theta, tile=10, ckpt=ckpt, k=3, ess_frac=0.9, trace_items=sample)
+    assert np.all(np.isfinite(ll))
+    _check_fp64(oracle, w, theta, ll, g, tr, k=3, ess_frac=0.9, items=sample)
+
+
+def test_mixed_optimal_proposal_within_tolerance(oracle):
+    w = _opt(synth.make(1, N=32, M=64, T=50))
+    theta = spread_theta(w, 0.1, seed=13)
+    items = [(0, i) for i in range(w.N)]
+    ll, g, tr = gpu_pf(w, theta, precision=smc2.MIXED, k=2, trace_items=items)
+    n_ok, _ = _mixed_report(oracle, w, theta, ll, g, tr, 2, items, w.name)
+    assert n_ok >= 0.9 * len(items)
+
+
+def test_optimal_proposal_estimates_sit_at_the_kalman_value(oracle):
+    """512 independent filters at one theta on the full-size data: both proposals' mean
+    likelihood estimate sits at the Kalman value (lognormal bias aside), and the optimal
+    proposal's spread is far smaller than the bootstrap filter's."""
+    w = synth.make(1, N=512)
+    th = np.tile(w.theta_true, (1, w.N, 1))
+    m = oracle.Model(smc2.LG1D, 1, 3)
+    lkf, _ = oracle.kalman(m, w.theta_true, w.y[0])
+    out = {}
+    for kind in (smc2.LG1D, smc2.LG1D_OPT):
+        w.kind = kind
+        ll, _, _ = gpu_pf(w, th, precision=smc2.MIXED, k=2, want_grad=0)
+        out[kind] = (ll[0].mean() - lkf, ll[0].std())
+        say("  kind %d: mean loglik - Kalman %.3f, sd %.3f" % (kind, *out[kind]))
+    assert abs(out[smc2.LG1D_OPT][0]) < 3 * out[smc2.LG1D_OPT][1] + 0.5 * out[smc2.LG1D_OPT][1] ** 2
+    assert out[smc2.LG1D_OPT][1] < 0.5 * out[smc2.LG1D][1]
