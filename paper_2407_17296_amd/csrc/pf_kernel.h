@@ -214,10 +214,14 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
 }
 
 template <typename R, class Model, int WAVES, int PPL>
-__global__ __launch_bounds__(WAVES * 64, (sizeof(R) == 4 && PPL <= 4 && WAVES <= 4) ? 4 : 1)
+__global__ __launch_bounds__(WAVES * 64,
+                             (sizeof(R) == 4 && Model::DX == 1 && PPL <= 4 && WAVES <= 4) ? 4 : 1)
 void pf_fwd_adj_kernel(PFArgs A) {
   constexpr int NT = WAVES * 64, MP = NT * PPL, DX = Model::DX, NP = Model::NP;
   constexpr double kNegInf = -__builtin_huge_val();
+  // the reverse sweep loads step t - 1 while step t is processed; a multi-dimensional state
+  // loads each step where it is used instead (its registers are the limit there)
+  constexpr bool kPrefetch = DX == 1;
   __shared__ double sh_P[MP];        // multinomial prefix
   __shared__ R sh_X[2][MP];          // gather / adjoint-scatter staging (ping-pong)
   __shared__ int sh_mark[MP + 64];   // systematic first-offspring markers + a dummy per lane
@@ -491,8 +495,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
     // One reverse step t: the weight adjoint restarts at resampled steps and at T, the state
     // adjoint is scatter-added from offspring to parents at resampled steps, then the step's
     // observation and transition are differentiated.  xp / xn: state before / after the step.
-    auto reverse_step = [&](int t, const R (&xp)[PPL][DX], const R (&xn)[PPL][DX],
-                            const R (&ce)[PPL][DX], const R (&cw)[PPL], const int (&ca)[PPL]) {
+    auto reverse_step = [&](int t, const R (&xp)[PPL][DX], const R (&ce)[PPL][DX],
+                            const R (&cw)[PPL], const int (&ca)[PPL]) {
       const R *yv = sh_y + (size_t)(t - 1) * DX;
       const bool res = t < T && sh_f[t - 1] != 0;
       if (t == T) {
@@ -536,7 +540,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
       for (int k = 0; k < NP; ++k) tp[k] = (R)0;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        mdl.advance_adj(yv, xp[p], xn[p], ce[p], wb[p], xb[p], tp);
+        R xn[DX];  // the state after the step, rebuilt where the adjoint needs it
+#pragma unroll
+        for (int q = 0; q < DX; ++q) xn[q] = xp[p][q];
+        (void)mdl.advance(xn, ce[p], yv);
+        mdl.advance_adj(yv, xp[p], xn, ce[p], wb[p], xb[p], tp);
       }
 #pragma unroll
       for (int k = 0; k < NP; ++k) tb[k] += (double)tp[k];
@@ -572,10 +580,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
           na[p] = lres ? anc[(size_t)(t - 1) * LD + j0 + p] : 0;
         }
       };
-      if (T > 0) load_trace(T);
+      if (kPrefetch && T > 0) load_trace(T);
       for (int t = T; t >= 1; --t) {
-        R cx[PPL][DX], xn[PPL][DX], ce[PPL][DX], cl[PPL], cw[PPL];
+        R cx[PPL][DX], ce[PPL][DX], cl[PPL], cw[PPL];
         int ca[PPL];
+        if (!kPrefetch) load_trace(t);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
 #pragma unroll
@@ -586,7 +595,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
           cl[p] = nl[p];
           ca[p] = na[p];
         }
-        if (t > 1) load_trace(t - 1);
+        if (kPrefetch && t > 1) load_trace(t - 1);
         if (!nz) filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, ce);
         mdl.per_step(t);
         const R *yv = sh_y + (size_t)(t - 1) * DX;
@@ -594,17 +603,17 @@ void pf_fwd_adj_kernel(PFArgs A) {
         const R st = (R)sh_s[t - 1];  // max_t + log S_t
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-          for (int q = 0; q < DX; ++q) xn[p][q] = cx[p][q];
-          const R lam = mdl.advance(xn[p], ce[p], yv);
           cw[p] = (R)0;
           if (need_w) {
-            R v = cl[p] + lam;
+            R xn[DX];
+#pragma unroll
+            for (int q = 0; q < DX; ++q) xn[q] = cx[p][q];
+            R v = cl[p] + mdl.advance(xn, ce[p], yv);
             if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
             cw[p] = fexp(v - st);
           }
         }
-        reverse_step(t, cx, xn, ce, cw, ca);
+        reverse_step(t, cx, ce, cw, ca);
       }
     } else {
       // segment rows of one step: x before the step (DX rows), the noise when it is not
@@ -697,10 +706,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
             na[p] = lres ? anc[(size_t)(t - 1) * LD + j0 + p] : 0;
           }
         };
-        load_step(t1);
+        if (kPrefetch) load_step(t1);
         for (int t = t1; t > t0; --t) {
-          R cx[PPL][DX], xn[PPL][DX], ce[PPL][DX], cw[PPL];
+          R cx[PPL][DX], ce[PPL][DX], cw[PPL];
           int ca[PPL];
+          if (!kPrefetch) load_step(t);
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
 #pragma unroll
@@ -711,16 +721,9 @@ void pf_fwd_adj_kernel(PFArgs A) {
             cw[p] = nw[p];
             ca[p] = na[p];
           }
-          if (t - 1 > t0) load_step(t - 1);
+          if (kPrefetch && t - 1 > t0) load_step(t - 1);
           mdl.per_step(t);
-          const R *yv = sh_y + (size_t)(t - 1) * DX;
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-            for (int q = 0; q < DX; ++q) xn[p][q] = cx[p][q];
-            (void)mdl.advance(xn[p], ce[p], yv);
-          }
-          reverse_step(t, cx, xn, ce, cw, ca);
+          reverse_step(t, cx, ce, cw, ca);
         }
       }
     }
