@@ -110,6 +110,70 @@ __device__ __forceinline__ double uniform_m(uint32_t c0, uint32_t c2, uint32_t c
   return ((double)v + 1.0) * 0x1p-32;
 }
 
+// ---- a lane's run of particle slots in HBM ------------------------------------------------------
+// A lane owns N consecutive slots of every per-particle row; the run starts at a multiple of its
+// own size in bytes, so it moves with the widest aligned vector accesses.
+template <int N, typename T>
+__device__ __forceinline__ void store_run(T *dst, const T (&v)[N]) {
+  constexpr int B = N * (int)sizeof(T);
+  if constexpr (B % 16 == 0) {
+#pragma unroll
+    for (int b = 0; b < B / 16; ++b) {
+      uint4 w;
+      __builtin_memcpy(&w, reinterpret_cast<const char *>(v) + 16 * b, 16);
+      reinterpret_cast<uint4 *>(dst)[b] = w;
+    }
+  } else if constexpr (B % 8 == 0) {
+#pragma unroll
+    for (int b = 0; b < B / 8; ++b) {
+      uint2 w;
+      __builtin_memcpy(&w, reinterpret_cast<const char *>(v) + 8 * b, 8);
+      reinterpret_cast<uint2 *>(dst)[b] = w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[i] = v[i];
+  }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void load_run(const T *src, T (&v)[N]) {
+  constexpr int B = N * (int)sizeof(T);
+  if constexpr (B % 16 == 0) {
+#pragma unroll
+    for (int b = 0; b < B / 16; ++b) {
+      const uint4 w = reinterpret_cast<const uint4 *>(src)[b];
+      __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * b, &w, 16);
+    }
+  } else if constexpr (B % 8 == 0) {
+#pragma unroll
+    for (int b = 0; b < B / 8; ++b) {
+      const uint2 w = reinterpret_cast<const uint2 *>(src)[b];
+      __builtin_memcpy(reinterpret_cast<char *>(v) + 8 * b, &w, 8);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = src[i];
+  }
+}
+
+// component q of a lane's particles, as a run
+template <int N, int DX, typename T>
+__device__ __forceinline__ void store_comp(T *dst, const T (&v)[N][DX], int q) {
+  T r[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = v[i][q];
+  store_run<N>(dst, r);
+}
+
+template <int N, int DX, typename T>
+__device__ __forceinline__ void load_comp(const T *src, T (&v)[N][DX], int q) {
+  T r[N];
+  load_run<N>(src, r);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i][q] = r[i];
+}
+
 // ---- wave and workgroup reductions ------------------------------------------------------------
 // Cross-lane moves use the data-parallel (DPP) modifiers of GFX9 VALU instructions instead of
 // LDS permutes: quad swaps and row mirrors for butterflies inside each row of 16 lanes, row

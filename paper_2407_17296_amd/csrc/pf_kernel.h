@@ -297,15 +297,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
 
     auto store_noise = [&](int t, const R (&e)[PPL][DX]) {
 #pragma unroll
-      for (int q = 0; q < DX; ++q)
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) nz[((size_t)t * DX + q) * LD + j0 + p] = e[p][q];
+      for (int q = 0; q < DX; ++q) store_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, e, q);
     };
     auto load_noise = [&](int t, R (&e)[PPL][DX]) {
 #pragma unroll
-      for (int q = 0; q < DX; ++q)
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) e[p][q] = nz[((size_t)t * DX + q) * LD + j0 + p];
+      for (int q = 0; q < DX; ++q) load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, e, q);
     };
 
     // ---- forward ------------------------------------------------------------------------------
@@ -327,11 +323,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
       if (ck_left == 0) {
         R *cks = ck + (size_t)ck_idx * (DX + 1) * LD;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-          for (int q = 0; q < DX; ++q) cks[q * LD + j0 + p] = x[p][q];
-          cks[DX * LD + j0 + p] = lW[p];
-        }
+        for (int q = 0; q < DX; ++q) store_comp<PPL>(cks + q * LD + j0, x, q);
+        store_run<PPL>(cks + DX * LD + j0, lW);
         ck_left = c;
         ++ck_idx;
       }
@@ -452,11 +445,9 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) x[p][q] = sx[a[p]];
       }
+      store_run<PPL>(anc + (size_t)(t - 1) * LD + j0, a);
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        anc[(size_t)(t - 1) * LD + j0 + p] = a[p];
-        lW[p] = lWeqR;
-      }
+      for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
     }
     if (dead) {
       if (tid == 0) A.loglik[item] = kNegInf;
@@ -570,15 +561,16 @@ void pf_fwd_adj_kernel(PFArgs A) {
         const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
         const bool lres = t < T && sh_f[t - 1] != 0;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-          for (int q = 0; q < DX; ++q) {
-            nx[p][q] = cks[q * LD + j0 + p];
-            if (nz) ne[p][q] = nz[((size_t)t * DX + q) * LD + j0 + p];
-          }
-          nl[p] = cks[DX * LD + j0 + p];
-          na[p] = lres ? anc[(size_t)(t - 1) * LD + j0 + p] : 0;
+        for (int q = 0; q < DX; ++q) {
+          load_comp<PPL>(cks + q * LD + j0, nx, q);
+          if (nz) load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ne, q);
         }
+        load_run<PPL>(cks + DX * LD + j0, nl);
+        if (lres)
+          load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, na);
+        else
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) na[p] = 0;
       };
       if (kPrefetch && T > 0) load_trace(T);
       for (int t = T; t >= 1; --t) {
@@ -626,20 +618,15 @@ void pf_fwd_adj_kernel(PFArgs A) {
         const int t0 = seg * c, t1 = min(T, t0 + c);
         const R *cks = ck + (size_t)seg * (DX + 1) * LD;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-          for (int q = 0; q < DX; ++q) x[p][q] = cks[q * LD + j0 + p];
-          lW[p] = cks[DX * LD + j0 + p];
-        }
+        for (int q = 0; q < DX; ++q) load_comp<PPL>(cks + q * LD + j0, x, q);
+        load_run<PPL>(cks + DX * LD + j0, lW);
         // recompute the segment with the stored ancestors and log normalisers
         R ne[PPL][DX];
         if (nz) load_noise(t0 + 1, ne);
         for (int t = t0 + 1; t <= t1; ++t) {
           const bool res = sh_f[t - 1] != 0;
           int a[PPL];
-          if (res)
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) a[p] = anc[(size_t)(t - 1) * LD + j0 + p];
+          if (res) load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, a);
           R e[PPL][DX];
           if (nz) {
 #pragma unroll
@@ -656,12 +643,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
           const R st = (R)sh_s[t - 1], mt = sh_mx[t - 1];  // max_t + log S_t, max_t
           R wv[PPL];
 #pragma unroll
-          for (int p = 0; p < PPL; ++p) {
+          for (int q = 0; q < DX; ++q) {
+            store_comp<PPL>(row + q * LD + j0, x, q);
+            if (!nz) store_comp<PPL>(row + (DX + q) * LD + j0, e, q);
+          }
 #pragma unroll
-            for (int q = 0; q < DX; ++q) {
-              row[q * LD + j0 + p] = x[p][q];
-              if (!nz) row[(DX + q) * LD + j0 + p] = e[p][q];
-            }
+          for (int p = 0; p < PPL; ++p) {
             R v = lW[p] + mdl.advance(x[p], e[p], yv);
             if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
             wv[p] = v;
@@ -669,7 +656,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
           if (t == T || res) {
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) row[WROW * LD + j0 + p] = fexp(wv[p] - st);
+            for (int p = 0; p < PPL; ++p) wv[p] = fexp(wv[p] - st);
+            store_run<PPL>(row + WROW * LD + j0, wv);
           }
           if (res) {
 #pragma unroll
@@ -695,16 +683,21 @@ void pf_fwd_adj_kernel(PFArgs A) {
           const R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
           const bool lres = t < T && sh_f[t - 1] != 0;
 #pragma unroll
-          for (int p = 0; p < PPL; ++p) {
-#pragma unroll
-            for (int q = 0; q < DX; ++q) {
-              nx[p][q] = row[q * LD + j0 + p];
-              ne[p][q] = nz ? nz[((size_t)t * DX + q) * LD + j0 + p]
-                            : row[(DX + q) * LD + j0 + p];
-            }
-            nw[p] = (t == T || lres) ? row[WROW * LD + j0 + p] : (R)0;
-            na[p] = lres ? anc[(size_t)(t - 1) * LD + j0 + p] : 0;
+          for (int q = 0; q < DX; ++q) {
+            load_comp<PPL>(row + q * LD + j0, nx, q);
+            load_comp<PPL>(nz ? nz + ((size_t)t * DX + q) * LD + j0 : row + (DX + q) * LD + j0,
+                           ne, q);
           }
+          if (t == T || lres)
+            load_run<PPL>(row + WROW * LD + j0, nw);
+          else
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) nw[p] = (R)0;
+          if (lres)
+            load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, na);
+          else
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) na[p] = 0;
         };
         if (kPrefetch) load_step(t1);
         for (int t = t1; t > t0; --t) {
