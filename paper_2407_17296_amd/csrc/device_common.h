@@ -31,6 +31,12 @@ __device__ __forceinline__ uint32_t stream_word(uint32_t k, uint32_t stream) {
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint64_t seed) {
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  // An empty statement that the compiler must assume changes the key: it then advances the key
+  // schedule (two scalar adds per round) inside every call instead of holding all twenty round
+  // keys in scalar registers for the whole kernel, which spilled scalar registers into vector
+  // lanes and cost the filter kernel up to a quarter of its time.  The seed is a kernel argument,
+  // uniform across the wave, which the scalar-register constraint requires.
+  asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
