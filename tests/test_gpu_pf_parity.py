@@ -349,3 +349,19 @@ def test_optimal_proposal_estimates_sit_at_the_kalman_value(oracle):
         say("  kind %d: mean loglik - Kalman %.3f, sd %.3f" % (kind, *out[kind]))
     assert abs(out[smc2.LG1D_OPT][0]) < 3 * out[smc2.LG1D_OPT][1] + 0.5 * out[smc2.LG1D_OPT][1] ** 2
     assert out[smc2.LG1D_OPT][1] < 0.5 * out[smc2.LG1D][1]
+
+
+@pytest.mark.parametrize("precision", [smc2.FP64, smc2.MIXED])
+def test_launches_are_reproducible(precision):
+    """Two launches on the same inputs give the same estimates bit for bit (the forward sweep
+    has a fixed order throughout); the gradients agree to rounding, the order in which the
+    adjoint's workgroup atomics add offspring into shared parents being the only difference."""
+    w = synth.make(1, N=64)
+    theta = spread_theta(w, 0.2, seed=14)
+    a = gpu_pf(w, theta, precision=precision, k=2, tile=10)
+    b = gpu_pf(w, theta, precision=precision, k=2, tile=10)
+    assert np.array_equal(a[0], b[0])
+    tol = 1e-12 if precision == smc2.FP64 else 1e-5
+    worst = max(rel_err(a[1][s, i], b[1][s, i]) for s in range(w.S) for i in range(w.N))
+    say("  relaunch: max relative gradient difference %.1e" % worst)
+    assert worst <= tol
