@@ -16,7 +16,7 @@
  *     Langevin proposal SMC1 of Sec. III-D, the L-kernel weight (eq. l_weights with the kernel of
  *     Sec. III-E), normalisation (eq. normalise_smc2), ESS (eq. ess_smc2) and resampling.
  * Readings where the paper is silent or garbled are listed with the design notes; each is named
- * at the line that takes it (C1..C23 numbering of the scope table).
+ * at the line that takes it (C1..C30 numbering of the design notes).
  *
  * Every loop is serial with the particle index ascending.  No blocking, no fusion.
  */
@@ -135,14 +135,32 @@ inline double re(const cplx &v) { return v.real(); }
  *                                     a x_{t-1}/sx^2), rho^2), 1/rho^2 = 1/sx^2 + 1/sy^2, and
  *                                     incremental weight p(y_t | x_{t-1}) =
  *                                     N(y_t; a x_{t-1}, sx^2 + sy^2) (C24)
+ *   SIR     (beta, gamma):            S_t = S - beta I S / N_pop + s_e e_0,
+ *                                     I_t = I + beta I S / N_pop - gamma I - s_e e_0 + s_e e_1,
+ *                                     y = I_t + s_y w,  x_0 = (N_pop - I_0, I_0)  (C28-C30)
  * The bootstrap proposal q = f is written in reparameterised form x = mu(x) + sqrt(C) e
  * (eq. reparam_epsilon), and the optimal proposal likewise x = m(x, y) + rho e.  Each routine also returns the partial derivatives that the tangent
  * recursion of eqs. df..dxk needs; they are only used by the real instantiation. */
+
+/* SIR constants (N_pop, I_0, s_e^2, s_y): the paper's population, initial infections and noise
+ * variance (Sec. IV-B), and the observation sd of C30 */
+const double kSirDefaults[4] = {763.0, 1.0, 0.5, 5.0};
+
+int obs_dim(const orc_model *m) { return m->kind == ORC_SIR ? 1 : m->d; }
 
 template <class R>
 struct Model {
   int kind, d, D;
   const R *th;
+  double np = 0, i0 = 0, se = 0, sy = 0; /* SIR: N_pop, I_0, s_e, s_y */
+
+  void set_constants(const double *c) {
+    const double *v = c ? c : kSirDefaults;
+    np = v[0];
+    i0 = v[1];
+    se = std::sqrt(v[2]);
+    sy = v[3];
+  }
 
   /* x_0 = m0(theta) + s0(theta) e_0;  dx0[q*D + p] = d x_0,q / d theta_p */
   void init(const double *e0, R *x, double *dx0) const {
@@ -157,6 +175,13 @@ struct Model {
       }
       return;
     }
+    if (kind == ORC_SIR) { /* deterministic start (Sec. IV-B): no dependence on theta */
+      x[0] = R(np - i0);
+      x[1] = R(i0);
+      if (dx0)
+        for (int r = 0; r < 2 * D; ++r) dx0[r] = 0.0;
+      return;
+    }
     for (int q = 0; q < d; ++q) {
       x[q] = R(e0[q]);
       if (dx0)
@@ -165,7 +190,7 @@ struct Model {
   }
 
   /* x_t = f(x_{t-1}, theta, e_t, t).  Tangent (eq. dxk): dx_new = F_x dx_old + F_theta.
-   * dx is [d][D], updated in place when non-NULL (F_x is diagonal for every model here). */
+   * dx is [d][D], updated in place when non-NULL (F_x is diagonal for every model but SIR). */
   void propagate(int t, R *x, const double *e, double *dx) const {
     switch (kind) {
       case ORC_LG1D: {
@@ -206,6 +231,25 @@ struct Model {
           double fx = 0.5 + 25.0 * (1.0 - xr * xr) / (den * den);
           dx[0] = fx * dx[0] + re(sx) * e[0];
           dx[1] = fx * dx[1];
+        }
+        break;
+      }
+      case ORC_SIR: {
+        /* new infections beta I S / N_pop move from S to I; recoveries gamma I leave I */
+        R beta = th[0], gam = th[1];
+        R So = x[0], Io = x[1];
+        R inf = beta * Io * So / np;
+        x[0] = So - inf + se * e[0];
+        x[1] = Io + inf - gam * Io - se * e[0] + se * e[1];
+        if (dx) {
+          double br = re(beta), gr = re(gam), sr = re(So), ir = re(Io);
+          for (int p = 0; p < D; ++p) {
+            double dS = dx[p], dI = dx[D + p];
+            /* d inf = (beta I / N) dS + (beta S / N) dI + (I S / N) d beta */
+            double dinf = br * ir / np * dS + br * sr / np * dI + (p == 0 ? ir * sr / np : 0.0);
+            dx[p] = dS - dinf;
+            dx[D + p] = dI + dinf - gr * dI - (p == 1 ? ir : 0.0);
+          }
         }
         break;
       }
@@ -299,6 +343,15 @@ struct Model {
         }
         return -kHalfLog2Pi - lsy - 0.5 * r * r;
       }
+      case ORC_SIR: { /* y = I_t + s_y w (C30) */
+        R r = (y[0] - x[1]) / sy;
+        if (dl_dx) {
+          dl_dx[0] = 0.0;
+          dl_dx[1] = re(r) / sy;
+          dl_dth[0] = dl_dth[1] = 0.0;
+        }
+        return -kHalfLog2Pi - std::log(sy) - 0.5 * r * r;
+      }
       case ORC_SV: {
         R ex = std::exp(-x[0]);
         if (dl_dx) {
@@ -320,6 +373,7 @@ bool model_ok(const orc_model *m) {
     case ORC_GROWTH: return m->d == 1 && m->D == 2;
     case ORC_SV: return m->d == 1 && m->D == 3;
     case ORC_LG1D_OPT: return m->d == 1 && m->D == 3;
+    case ORC_SIR: return m->d == 2 && m->D == 2;
   }
   return false;
 }
@@ -354,6 +408,8 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
   const bool tangent = std::is_same<R, double>::value && grad != nullptr;
   const int d = mdl->d, D = mdl->D;
   Model<R> mod{mdl->kind, d, D, theta};
+  mod.set_constants(mdl->constants);
+  const int dy = obs_dim(mdl);
 
   if (anc)
     for (long i = 0; i < (long)T * M; ++i) anc[i] = -1;
@@ -397,7 +453,7 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
   R ll = R(0.0);
   std::vector<double> lld(D, 0.0);
   for (int t = 1; t <= T; ++t) {
-    const double *yt = y + (size_t)(t - 1) * d;
+    const double *yt = y + (size_t)(t - 1) * dy;
     /* propagate with the bootstrap proposal and weight by g (eq. priorproposalweight) */
     for (int j = 0; j < M; ++j) {
       for (int q = 0; q < d; ++q)
@@ -609,6 +665,14 @@ int orc_kalman(const orc_model *mdl, const double *theta, int32_t T, const doubl
 double orc_log_prior(const orc_model *mdl, const double *theta, double *grad) {
   double lp = 0.0;
   for (int p = 0; p < mdl->D; ++p) {
+    if (mdl->prior_kind && mdl->prior_kind[p] == ORC_PRIOR_KIND_UNIFORM) {
+      /* U(lo, hi): constant density on the closed interval, zero outside; the gradient of
+       * its log is zero wherever it is finite */
+      double lo = mdl->prior_mu[p], hi = mdl->prior_sd[p];
+      lp += (theta[p] >= lo && theta[p] <= hi) ? -std::log(hi - lo) : kNegInf;
+      if (grad) grad[p] = 0.0;
+      continue;
+    }
     double sd = mdl->prior_sd[p], z = (theta[p] - mdl->prior_mu[p]) / sd;
     lp += -kHalfLog2Pi - std::log(sd) - 0.5 * z * z;
     if (grad) grad[p] = -z / sd;
@@ -704,11 +768,16 @@ int orc_smc2_run(const orc_model *mdl, const orc_pf_opts *pf, const orc_smc2_opt
     if (k == 1) {
       /* eq. init_sample: theta_1 ~ q_1 = prior */
       for (int i = 0; i < N; ++i)
-        for (int p = 0; p < D; ++p)
-          thn[i * D + p] = mdl->prior_mu[p] +
-                           mdl->prior_sd[p] * normal_n(seed, 0xFFFFFFFFu,
-                                                       (uint32_t)(so->series * N + i),
-                                                       c3_of(1, ORC_PRIOR_NORMAL), (uint32_t)p);
+        for (int p = 0; p < D; ++p) {
+          const uint32_t c2 = (uint32_t)(so->series * N + i), c3 = c3_of(1, ORC_PRIOR_NORMAL);
+          if (mdl->prior_kind && mdl->prior_kind[p] == ORC_PRIOR_KIND_UNIFORM) {
+            double lo = mdl->prior_mu[p], hi = mdl->prior_sd[p];
+            thn[i * D + p] = lo + (hi - lo) * uniform_m(seed, 0xFFFFFFFFu, c2, c3, (uint32_t)p);
+          } else {
+            thn[i * D + p] = mdl->prior_mu[p] +
+                             mdl->prior_sd[p] * normal_n(seed, 0xFFFFFFFFu, c2, c3, (uint32_t)p);
+          }
+        }
     } else {
       for (int i = 0; i < N; ++i) {
         for (int p = 0; p < D; ++p)
@@ -731,7 +800,7 @@ int orc_smc2_run(const orc_model *mdl, const orc_pf_opts *pf, const orc_smc2_opt
              &lln[i], &gll[i * D], nullptr, nullptr, nullptr);
       /* log posterior and its gradient (eqs. log_posterior, first_gradientlogposterior) */
       double lp = orc_log_prior(mdl, &thn[i * D], lprior_g.data());
-      lpin[i] = lp + lln[i];
+      lpin[i] = lp == kNegInf ? kNegInf : lp + lln[i]; /* outside the prior's support: 0 */
       for (int p = 0; p < D; ++p) gpin[i * D + p] = lprior_g[p] + gll[i * D + p];
     }
     /* weights: eq. init_weights at k = 1 (q_1 = prior, so w = likelihood; C13), eq. l_weights

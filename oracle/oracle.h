@@ -18,7 +18,10 @@
  *   - Per-sample streams (prior, move, outer resampling): c0 = 0xFFFFFFFF, normal n in block
  *     n / 4 (c1), uniform m in block m / 4.
  *   - Box-Muller (Box & Muller 1958) on word pairs; uniforms (w + 1) * 2^-32 in (0, 1].
- *   - Arrays are row-major; y is [T][d]; theta is [D]; ancestors are [T][M] int32.
+ *   - Arrays are row-major; y is [T][d_y] (d_y = d, or 1 for ORC_SIR); theta is [D];
+ *     ancestors are [T][M] int32.
+ *   - Prior draws: normal n = p of the prior stream of sample i (normal parameters), uniform
+ *     m = p of the same stream (uniform parameters).
  */
 #ifndef SMC2_ORACLE_H
 #define SMC2_ORACLE_H
@@ -30,17 +33,27 @@ extern "C" {
 #endif
 
 /* model kinds (same numbering as the library's smc2_model_kind, written out again here) */
-enum { ORC_LG1D = 0, ORC_LG_DIAG = 1, ORC_GROWTH = 2, ORC_SV = 3, ORC_LG1D_OPT = 4 };
+enum { ORC_LG1D = 0, ORC_LG_DIAG = 1, ORC_GROWTH = 2, ORC_SV = 3, ORC_LG1D_OPT = 4, ORC_SIR = 5 };
+/* prior kinds per parameter: N(prior_mu, prior_sd^2), or uniform on (prior_mu, prior_sd) */
+enum { ORC_PRIOR_KIND_NORMAL = 0, ORC_PRIOR_KIND_UNIFORM = 1 };
 /* random streams of the counter contract */
 enum { ORC_INIT_NORMAL = 1, ORC_STEP_NORMAL = 2, ORC_RESAMPLE_UNIFORM = 3, ORC_PRIOR_NORMAL = 4,
        ORC_MOVE_NORMAL = 5, ORC_OUTER_RESAMPLE_UNIFORM = 6 };
 enum { ORC_SYSTEMATIC = 0, ORC_MULTINOMIAL = 1 };
 
+/* ORC_SIR: the discrete-time SIR model of Sec. IV-B, state x = (S, I) (R = N_pop - S - I),
+ * theta = (beta, gamma) on their natural scale:
+ *   S_t = S - beta I S / N_pop + s_e e_b,   I_t = I + beta I S / N_pop - gamma I - s_e e_b + s_e e_g,
+ *   y_t = I_t + s_y w  (one observation per step),   x_0 = (N_pop - I_0, I_0),
+ * with the model constants (N_pop, I_0, s_e^2, s_y), default (763, 1, 0.5, 5) (C28-C30). */
 typedef struct {
   int32_t kind;      /* ORC_* model kind */
-  int32_t d;         /* state dimension (1, or 16 for ORC_LG_DIAG) */
+  int32_t d;         /* state dimension (1, 2 for ORC_SIR, or 16 for ORC_LG_DIAG) */
   int32_t D;         /* parameter dimension */
-  const double *prior_mu, *prior_sd; /* [D] independent Gaussian prior */
+  const double *prior_mu, *prior_sd; /* [D] independent priors: mean and sd (normal) or the
+                                        lower and upper bound (uniform) */
+  const int32_t *prior_kind;         /* [D] ORC_PRIOR_KIND_* or NULL: every parameter normal */
+  const double *constants;           /* model constants (ORC_SIR: 4 values) or NULL: defaults */
 } orc_model;
 
 typedef struct {

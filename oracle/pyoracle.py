@@ -13,7 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.cpp")
 
-LG1D, LG_DIAG, GROWTH, SV, LG1D_OPT = 0, 1, 2, 3, 4
+LG1D, LG_DIAG, GROWTH, SV, LG1D_OPT, SIR = 0, 1, 2, 3, 4, 5
+PRIOR_KIND_NORMAL, PRIOR_KIND_UNIFORM = 0, 1
 INIT_NORMAL, STEP_NORMAL, RESAMPLE_UNIFORM, PRIOR_NORMAL, MOVE_NORMAL, OUTER_RESAMPLE_UNIFORM = (
     1, 2, 3, 4, 5, 6)
 SYSTEMATIC, MULTINOMIAL = 0, 1
@@ -33,7 +34,9 @@ def build(force=True):
 class _Model(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("d", ctypes.c_int32), ("D", ctypes.c_int32),
                 ("prior_mu", ctypes.POINTER(ctypes.c_double)),
-                ("prior_sd", ctypes.POINTER(ctypes.c_double))]
+                ("prior_sd", ctypes.POINTER(ctypes.c_double)),
+                ("prior_kind", ctypes.POINTER(ctypes.c_int32)),
+                ("constants", ctypes.POINTER(ctypes.c_double))]
 
 
 class _PFOpts(ctypes.Structure):
@@ -109,13 +112,21 @@ def _f64(a):
 
 
 class Model:
-    """Model description for the oracle: kind, state dim d, parameter dim D, Gaussian prior."""
+    """Model description for the oracle: kind, state dim d, parameter dim D, independent priors
+    (normal by default; prior_kind[p] = PRIOR_KIND_UNIFORM reads prior_mu[p], prior_sd[p] as the
+    bounds) and the model constants (None: the model's defaults)."""
 
-    def __init__(self, kind, d, D, prior_mu=None, prior_sd=None):
+    def __init__(self, kind, d, D, prior_mu=None, prior_sd=None, prior_kind=None,
+                 constants=None):
         self.kind, self.d, self.D = int(kind), int(d), int(D)
+        self.dy = 1 if self.kind == SIR else self.d
         self.prior_mu = _f64(np.zeros(D) if prior_mu is None else prior_mu)
         self.prior_sd = _f64(np.ones(D) if prior_sd is None else prior_sd)
-        self._s = _Model(self.kind, self.d, self.D, _dp(self.prior_mu), _dp(self.prior_sd))
+        self.prior_kind = (None if prior_kind is None
+                           else np.ascontiguousarray(prior_kind, dtype=np.int32))
+        self.constants = None if constants is None else _f64(constants)
+        self._s = _Model(self.kind, self.d, self.D, _dp(self.prior_mu), _dp(self.prior_sd),
+                         _ip(self.prior_kind), _dp(self.constants))
 
     @property
     def ref(self):
@@ -160,7 +171,7 @@ def pf(model, theta, y, M, seed, k, filter_id, resampler=SYSTEMATIC, ess_frac=0.
     """Run the oracle CRN-PF.  Returns dict(loglik, grad, ancestors, flags, s)."""
     theta = _f64(theta)
     y = _f64(y).reshape(-1)
-    T = len(y) // model.d if model.d else 0
+    T = len(y) // model.dy if model.dy else 0
     opts = _PFOpts(int(resampler), float(ess_frac))
     ll = ctypes.c_double(0.0)
     grad = np.zeros(model.D) if want_grad else None
@@ -180,7 +191,7 @@ def pf_complex_step(model, theta, y, M, seed, k, filter_id, p, h=1e-30, resample
                     ess_frac=0.5):
     theta = _f64(theta)
     y = _f64(y).reshape(-1)
-    T = len(y) // model.d
+    T = len(y) // model.dy
     opts = _PFOpts(int(resampler), float(ess_frac))
     ll = ctypes.c_double(0.0)
     dl = ctypes.c_double(0.0)
@@ -196,7 +207,7 @@ def pf_complex_step(model, theta, y, M, seed, k, filter_id, p, h=1e-30, resample
 def kalman(model, theta, y):
     theta = _f64(theta)
     y = _f64(y).reshape(-1)
-    T = len(y) // model.d
+    T = len(y) // model.dy
     ll = ctypes.c_double(0.0)
     grad = np.zeros(model.D)
     rc = lib().orc_kalman(model.ref, _dp(theta), T, _dp(y), ctypes.byref(ll), _dp(grad))
@@ -247,7 +258,7 @@ def smc2_run(model, y, N, M, K, gamma, seed, series=0, resampler=SYSTEMATIC, ess
              proposal=1):
     """Full oracle SMC^2 run on one series; returns the per-iteration records."""
     y = _f64(y).reshape(-1)
-    T = len(y) // model.d
+    T = len(y) // model.dy
     D = model.D
     opts = _PFOpts(int(resampler), float(ess_frac))
     so = _SMC2Opts(int(N), int(M), int(K), int(series), float(gamma), int(seed), int(proposal))

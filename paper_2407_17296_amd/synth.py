@@ -20,16 +20,24 @@ gamma; Sec. II and Sec. III) at the sizes of the project's benchmark table:
   4  SV       x_t = mu + phi (x - mu) + s v, y = exp(x/2) w, (mu, phi, s) = (-1, 0.95, 0.25),
               S = 64 series with T_s ~ U{50..1000},                          N = 256, M = 256,
               K = 10
+  5  SIR      the discrete SIR model of Sec. IV-B (state (S, I), N_pop = 763, I_0 = 1, noise
+              variance 0.5) observed as y = I + 5 w, (beta, gamma) = (0.6, 0.3), T = 35, N = 64,
+              M = 250, K = 15: the paper's outbreak experiment with simulated data in place of
+              its outbreak record
 
-Parameters are sampled in unconstrained coordinates (log of scales, atanh of phi) under an
-independent N(0, 1) prior.  data_seed = 20240724 + i, run seed = 17296 + i.
+Workloads 0-4 sample parameters in unconstrained coordinates (log of scales, atanh of phi) under
+an independent N(0, 1) prior; workload 5 samples (beta, gamma) on their natural scale under the
+paper's independent U(0, 1) priors.  data_seed = 20240724 + i, run seed = 17296 + i.
 """
 from dataclasses import dataclass, field
 
 import numpy as np
 
-LG1D, LG_DIAG, GROWTH, SV = 0, 1, 2, 3
-MODEL_NAMES = {LG1D: "lg1d", LG_DIAG: "lg_diag16", GROWTH: "growth", SV: "sv"}
+LG1D, LG_DIAG, GROWTH, SV, SIR = 0, 1, 2, 3, 5
+MODEL_NAMES = {LG1D: "lg1d", LG_DIAG: "lg_diag16", GROWTH: "growth", SV: "sv", SIR: "sir"}
+PRIOR_KIND_NORMAL, PRIOR_KIND_UNIFORM = 0, 1
+# SIR model constants: population, initial infections, process-noise variance, observation sd
+SIR_CONSTANTS = (763.0, 1.0, 0.5, 5.0)
 
 
 @dataclass
@@ -51,6 +59,13 @@ class Workload:
     prior_sd: np.ndarray = field(default=None)
     seed: int = 0
     data_seed: int = 0
+    dy: int = 0                     # observation dimension (0: equal to d)
+    prior_kind: np.ndarray = field(default=None)  # [D] PRIOR_KIND_*, None: all normal
+    constants: np.ndarray = field(default=None)   # model constants, None: the defaults
+
+    def __post_init__(self):
+        if not self.dy:
+            self.dy = self.d
 
     @property
     def T_max(self):
@@ -88,6 +103,16 @@ def _simulate(kind, theta, T, d, rng):
         for t in range(T):
             x = mu + phi * (x - mu) + s * rng.standard_normal()
             y[t, 0] = np.exp(x / 2) * rng.standard_normal()
+    elif kind == SIR:
+        beta, gam = theta[0], theta[1]
+        npop, i0, var, sy = SIR_CONSTANTS
+        se = np.sqrt(var)
+        S, I = npop - i0, i0
+        for t in range(T):
+            e = rng.standard_normal(2)
+            inf = beta * I * S / npop
+            S, I = S - inf + se * e[0], I + inf - gam * I - se * e[0] + se * e[1]
+            y[t, 0] = I + sy * rng.standard_normal()
     else:
         raise ValueError(kind)
     return y
@@ -120,8 +145,12 @@ def make(index, N=None, M=None, K=None, S=None, T=None):
         th = np.array([-1.0, np.arctanh(0.95), np.log(0.25)])
         Ss, Nn, Mm, Kk, gam = 64, 256, 256, 10, 0.05
         Ts = list(rng.integers(50, 1001, size=Ss))
+    elif i == 5:
+        kind, d, D = SIR, 2, 2
+        th = np.array([0.6, 0.3])
+        Ss, Ts, Nn, Mm, Kk, gam = 1, [35], 64, 250, 15, 0.006
     else:
-        raise ValueError("workload index must be 0..4")
+        raise ValueError("workload index must be 0..5")
     if S is not None:
         Ss = int(S)
         Ts = (list(Ts) * Ss)[:Ss]
@@ -129,18 +158,29 @@ def make(index, N=None, M=None, K=None, S=None, T=None):
         Ts = [min(int(t), int(T)) for t in Ts]
     T_len = np.asarray(Ts, dtype=np.int32)
     T_max = int(T_len.max())
-    y = np.zeros((Ss, T_max, d))
+    dy = 1 if kind == SIR else d
+    y = np.zeros((Ss, T_max, dy))
     for s in range(Ss):
-        y[s, :T_len[s]] = _simulate(kind, th, int(T_len[s]), d, rng)
-    return Workload(index=i, name=f"config{i}_{MODEL_NAMES[kind]}", kind=kind, d=d, D=D, S=Ss,
-                    N=int(N or Nn), M=int(M or Mm), K=int(K or Kk), gamma=float(gam),
-                    T_len=T_len, y=y, theta_true=th, prior_mu=np.zeros(D), prior_sd=np.ones(D),
-                    seed=seed, data_seed=data_seed)
+        y[s, :T_len[s]] = _simulate(kind, th, int(T_len[s]), dy, rng)
+    extra = {}
+    if kind == SIR:  # U(0, 1) priors: the bounds ride in prior_mu / prior_sd
+        extra = dict(prior_mu=np.zeros(D), prior_sd=np.ones(D), dy=1,
+                     prior_kind=np.full(D, PRIOR_KIND_UNIFORM, dtype=np.int32),
+                     constants=np.array(SIR_CONSTANTS))
+    name = f"config{i}_{MODEL_NAMES[kind]}" if i < 5 else "sir_outbreak_synthetic"
+    return Workload(index=i, name=name, kind=kind, d=d, D=D, S=Ss, N=int(N or Nn),
+                    M=int(M or Mm), K=int(K or Kk), gamma=float(gam), T_len=T_len, y=y,
+                    theta_true=th, seed=seed, data_seed=data_seed,
+                    **({"prior_mu": np.zeros(D), "prior_sd": np.ones(D)} | extra))
 
 
 def prior_draws(w, rng_seed=None, count=None):
-    """Independent N(prior_mu, prior_sd) draws [S][N][D] from numpy's generator, for tests that
-    want parameters without running the sampler's own prior stream."""
+    """Independent prior draws [S][N][D] from numpy's generator (normal, or uniform between the
+    bounds), for tests that want parameters without running the sampler's own prior stream."""
     rng = np.random.default_rng(w.seed if rng_seed is None else rng_seed)
     n = w.N if count is None else int(count)
-    return w.prior_mu + w.prior_sd * rng.standard_normal((w.S, n, w.D))
+    z = w.prior_mu + w.prior_sd * rng.standard_normal((w.S, n, w.D))
+    if w.prior_kind is not None:
+        u = w.prior_mu + (w.prior_sd - w.prior_mu) * rng.uniform(size=(w.S, n, w.D))
+        z = np.where(np.asarray(w.prior_kind) == PRIOR_KIND_UNIFORM, u, z)
+    return z
