@@ -130,7 +130,7 @@ def cpu_baseline(w, seconds, threads):
     import pyoracle
     if not os.path.exists(pyoracle.LIB_PATH):
         pyoracle.build()
-    m = pyoracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+    m = pyoracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd, w.prior_kind, w.constants)
     rng = np.random.default_rng(w.seed)
     thetas = w.theta_true + 0.1 * rng.standard_normal((w.N, w.D))
     y = w.y[0, :w.T_len[0]]

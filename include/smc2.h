@@ -66,20 +66,38 @@ typedef enum {
  *                      Sec. IV-A instead of the bootstrap one: x_t ~ N(rho^2 (y_t/sy^2 +
  *                      a x_{t-1}/sx^2), rho^2) with 1/rho^2 = 1/sx^2 + 1/sy^2, weighted by the
  *                      predictive density N(y_t; a x_{t-1}, sx^2 + sy^2)
- * with v, w ~ N(0, 1).  The prior p(theta) is independent N(prior_mu[p], prior_sd[p]^2). */
+ *   SMC2_MODEL_SIR     d_x=2, d_y=1, D=2: theta = (beta, gamma) on their natural scale; the
+ *                      discrete-time SIR model of Sec. IV-B with state (S, I):
+ *                      S_t = S - beta I S / N_pop + s_e v_1,
+ *                      I_t = I + beta I S / N_pop - gamma I - s_e v_1 + s_e v_2,
+ *                      y_t = I_t + s_y w, x_0 = (N_pop - I_0, I_0); the constants
+ *                      (N_pop, I_0, s_e^2, s_y) default to (763, 1, 0.5, 5).  The paper prints
+ *                      the infection term without the division by N_pop and states no
+ *                      observation model; these are readings, as is s_e^2 = 0.5 for N(0, 0.5).
+ * with v, w ~ N(0, 1).  The prior p(theta) is independent over the parameters: N(prior_mu[p],
+ * prior_sd[p]^2), or, where prior_kind[p] = SMC2_PRIOR_UNIFORM, uniform on the closed interval
+ * [prior_mu[p], prior_sd[p]] (the SIR model's priors are U(0, 1), Sec. IV-B).  A sample outside
+ * a uniform prior's support has posterior zero: its outer weight is zero. */
 typedef enum {
   SMC2_MODEL_LG1D = 0,
   SMC2_MODEL_LG_DIAG = 1,
   SMC2_MODEL_GROWTH = 2,
   SMC2_MODEL_SV = 3,
-  SMC2_MODEL_LG1D_OPT = 4
+  SMC2_MODEL_LG1D_OPT = 4,
+  SMC2_MODEL_SIR = 5
 } smc2_model_kind;
+
+typedef enum { SMC2_PRIOR_NORMAL = 0, SMC2_PRIOR_UNIFORM = 1 } smc2_prior_kind;
 
 typedef struct {
   int32_t kind;             /* smc2_model_kind */
-  int32_t d_x, d_y, D;      /* state dim, observation dim (= d_x), parameter dim */
-  const double *prior_mu;   /* host [D] */
-  const double *prior_sd;   /* host [D], > 0 */
+  int32_t d_x, d_y, D;      /* state dim, observation dim (d_x, or 1 for SIR), parameter dim */
+  const double *prior_mu;   /* host [D]: mean (normal) or lower bound (uniform), finite */
+  const double *prior_sd;   /* host [D]: sd > 0 (normal) or upper bound > lower (uniform) */
+  const int32_t *prior_kind; /* host [D] smc2_prior_kind, or NULL: every parameter normal */
+  const double *constants;  /* host, the model's constants (SIR: 4 values), or NULL for the
+                               defaults; ignored by the models that have none.  The values are
+                               copied at each call that takes the model. */
 } smc2_model;
 
 typedef enum { SMC2_FP64 = 0, SMC2_MIXED = 1 } smc2_precision;
@@ -222,7 +240,9 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
 /* ---- initialisation and inspection ------------------------------------------------------- */
 
 /* theta_1 ~ prior (eq. init_sample with q_1 = prior): theta[s][i][p] = prior_mu[p] +
- * prior_sd[p] * z, z from the PRIOR stream (iteration 1).  theta dev [S][N][D] out. */
+ * prior_sd[p] * z with z normal number p of the PRIOR stream of sample s*N+i (iteration 1), or,
+ * for a uniform parameter, prior_mu[p] + (prior_sd[p] - prior_mu[p]) * u with u uniform number p
+ * of the same stream.  theta dev [S][N][D] out. */
 smc2_status smc2_prior_init(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,
                             uint64_t seed, double *theta, void *stream);
 

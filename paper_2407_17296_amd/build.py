@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build", "smc2")
 LIB = os.path.join(PKG, "libsmc2.so")
 
 SOURCES = ["smc2_api.hip", "pf_lg1d.hip", "pf_growth.hip", "pf_sv.hip", "pf_lgdiag.hip",
-           "pf_lg1dopt.hip"]
+           "pf_lg1dopt.hip", "pf_sir.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

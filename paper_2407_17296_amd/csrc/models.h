@@ -7,6 +7,9 @@
 // log-density log g(y_t | x_t, theta); the optimal proposal of the 1-D LG model (Sec. IV-A)
 // moves by q(x_t | x_{t-1}, y_t) and weighs by p(y_t | x_{t-1}).
 //
+// `setup` receives the parameters (FP64) and the model constants (FP64, only the SIR model has
+// any).  DX / DY / NP: state, observation and parameter dimensions.
+//
 // R is the arithmetic type of propagation and weighting (double in the plain FP64 form, float
 // in the mixed form).  Parameters arrive in FP64 and are transformed once in FP64.  Gradient
 // contributions are added into accumulators `tb` indexed like theta (type Acc: the kernel
@@ -57,9 +60,9 @@ struct Bootstrap {
 // x_t = a x + sx e;  y = x + sy w;  theta = (a, log sx, log sy);  x_0 ~ N(0, 1).
 template <typename R>
 struct ModelLG1D : Bootstrap<ModelLG1D<R>, R> {
-  static constexpr int DX = 1, NP = 3;
+  static constexpr int DX = 1, DY = 1, NP = 3;
   R a, sx, c0, isy;  // c0 = -log(2 pi)/2 - log sy
-  __device__ void setup(const double *th) {
+  __device__ void setup(const double *th, const double *) {
     a = (R)th[0];
     sx = (R)exp(th[1]);
     c0 = (R)(-kHalfLog2Pi - th[2]);
@@ -93,9 +96,9 @@ struct ModelLG1D : Bootstrap<ModelLG1D<R>, R> {
 // x_0 ~ N(0, I).  A is diagonal, so the transition is elementwise.
 template <typename R, int D_X>
 struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
-  static constexpr int DX = D_X, NP = D_X + 2;
+  static constexpr int DX = D_X, DY = D_X, NP = D_X + 2;
   R A[D_X], sx, c0, isy;  // c0 = d (-log(2 pi)/2 - log sy)
-  __device__ void setup(const double *th) {
+  __device__ void setup(const double *th, const double *) {
 #pragma unroll
     for (int q = 0; q < D_X; ++q) A[q] = (R)th[q];
     sx = (R)exp(th[D_X]);
@@ -149,9 +152,9 @@ struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
 // theta = (log sx, log sy);  x_0 ~ N(0, 1).
 template <typename R>
 struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
-  static constexpr int DX = 1, NP = 2;
+  static constexpr int DX = 1, DY = 1, NP = 2;
   R sx, c0, isy, drive;  // c0 = -log(2 pi)/2 - log sy
-  __device__ void setup(const double *th) {
+  __device__ void setup(const double *th, const double *) {
     sx = (R)exp(th[0]);
     c0 = (R)(-kHalfLog2Pi - th[1]);
     isy = (R)exp(-th[1]);
@@ -188,9 +191,9 @@ struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
 // x_0 ~ N(mu, s^2 / (1 - phi^2)) = mu + s cosh(theta_1) e_0.
 template <typename R>
 struct ModelSV : Bootstrap<ModelSV<R>, R> {
-  static constexpr int DX = 1, NP = 3;
+  static constexpr int DX = 1, DY = 1, NP = 3;
   R mu, phi, s, sd0, dsd0;  // dsd0 = d sd0 / d theta_1 = s sinh(theta_1)
-  __device__ void setup(const double *th) {
+  __device__ void setup(const double *th, const double *) {
     mu = (R)th[0];
     phi = (R)tanh(th[1]);
     s = (R)exp(th[2]);
@@ -229,11 +232,11 @@ struct ModelSV : Bootstrap<ModelSV<R>, R> {
 // step.  theta = (a, log sx, log sy); x_0 ~ N(0, 1).
 template <typename R>
 struct ModelLG1DOpt {
-  static constexpr int DX = 1, NP = 3;
+  static constexpr int DX = 1, DY = 1, NP = 3;
   // kx = dm/dx = rho^2 a / sx^2, ky = rho^2 / sy^2, rx = rho^2 / sx^2, c0 = -log(2 pi)/2 -
   // log(s2)/2 and is2 = 1/s2 with s2 = sx^2 + sy^2, fx / fy = sx^2 / s2, sy^2 / s2
   R a, kx, ky, rx, rho, c0, is2, fx, fy;
-  __device__ void setup(const double *th) {
+  __device__ void setup(const double *th, const double *) {
     const double vx = exp(2.0 * th[1]), vy = exp(2.0 * th[2]);
     const double rho2 = 1.0 / (1.0 / vx + 1.0 / vy), s2 = vx + vy;
     a = (R)th[0];
@@ -270,6 +273,58 @@ struct ModelLG1DOpt {
     tb[1] += (Acc)mulz(g, rx * fmar((R)2, m - a * x, rho * e[0]));
     tb[2] += (Acc)mulz(g, ky * fmar((R)2, m - y[0], rho * e[0]));
     xb[0] = fmar(kx, g, mulz(wb, a * r * is2));
+  }
+};
+
+// The discrete-time SIR model of Sec. IV-B: state (S, I), R = N_pop - S - I implied,
+//   S_t = S - beta I S / N_pop + s_e e_0,  I_t = I + beta I S / N_pop - gamma I - s_e e_0 + s_e e_1,
+//   y = I_t + s_y w,  x_0 = (N_pop - I_0, I_0);  theta = (beta, gamma) on their natural scale.
+// Constants (N_pop, I_0, s_e^2, s_y).  The start is fixed, so init_adj has nothing to add.
+template <typename R>
+struct ModelSIR : Bootstrap<ModelSIR<R>, R> {
+  static constexpr int DX = 2, DY = 1, NP = 2;
+  R beta, gam, bn, s0, i0, se, isy, c0;  // bn = beta / N_pop, c0 = -log(2 pi)/2 - log s_y
+  R inp;                                 // 1 / N_pop
+  __device__ void setup(const double *th, const double *mc) {
+    beta = (R)th[0];
+    gam = (R)th[1];
+    bn = (R)(th[0] / mc[0]);
+    inp = (R)(1.0 / mc[0]);
+    s0 = (R)(mc[0] - mc[1]);
+    i0 = (R)mc[1];
+    se = (R)sqrt(mc[2]);
+    isy = (R)(1.0 / mc[3]);
+    c0 = (R)(-kHalfLog2Pi - log(mc[3]));
+  }
+  __device__ void per_step(int) {}
+  __device__ void init(const R *, R *x) const {
+    x[0] = s0;
+    x[1] = i0;
+  }
+  __device__ void init_adj(const R *, const R *, double *) const {}
+  __device__ void step(R *x, const R *e) const {
+    const R S = x[0], I = x[1];
+    const R inf = bn * I * S;  // new infections
+    x[0] = fmar(se, e[0], S - inf);
+    x[1] = fmar(se, e[1] - e[0], fmar(-gam, I, I) + inf);
+  }
+  // inf enters S with -1 and I with +1, so its adjoint is xb_I - xb_S
+  template <typename Acc>
+  __device__ void step_adj(const R *xp, const R *, R *xb, Acc *tb) const {
+    const R S = xp[0], I = xp[1], gS = xb[0], gI = xb[1];
+    const R d = gI - gS;
+    tb[0] += (Acc)mulz(d, I * S * inp);
+    tb[1] -= (Acc)mulz(gI, I);
+    xb[0] = fmar(bn * I, d, gS);
+    xb[1] = fmar(bn * S, d, fmar(-gam, gI, gI));
+  }
+  __device__ R logg(const R *y, const R *x) const {
+    const R r = (y[0] - x[1]) * isy;
+    return fmar((R)-0.5 * r, r, c0);
+  }
+  template <typename Acc>
+  __device__ void logg_adj(const R *y, const R *x, R wb, R *xb, Acc *) const {
+    xb[1] += mulz(wb, (y[0] - x[1]) * isy * isy);
   }
 };
 

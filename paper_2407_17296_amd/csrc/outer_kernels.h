@@ -10,18 +10,25 @@ namespace smc2 {
 
 constexpr int kMaxD = 32;
 
+// Independent priors: kind 0 N(mu, sd^2); kind 1 uniform on [mu, sd] (lower, upper bound).
 struct Prior {
   double mu[kMaxD], sd[kMaxD];
+  int kind[kMaxD];
 };
 
-// theta_1 ~ prior (eq. init_sample with q_1 = prior): one thread per (s, i).
+// theta_1 ~ prior (eq. init_sample with q_1 = prior): one thread per (s, i); normal number p of
+// the sample's prior stream for a normal parameter, uniform number p for a uniform one.
 __global__ void prior_init_kernel(int n_items, int D, Prior pr, uint64_t seed, double *theta) {
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= n_items) return;
   const uint32_t c3 = stream_word(1u, kStreamPrior);
   for (int p = 0; p < D; ++p)
     theta[(size_t)item * D + p] =
-        pr.mu[p] + pr.sd[p] * normal_n<double>(kNoSlot, (uint32_t)item, c3, (uint32_t)p, seed);
+        pr.kind[p] == 1
+            ? pr.mu[p] + (pr.sd[p] - pr.mu[p]) *
+                             uniform_m(kNoSlot, (uint32_t)item, c3, (uint32_t)p, seed)
+            : pr.mu[p] + pr.sd[p] * normal_n<double>(kNoSlot, (uint32_t)item, c3, (uint32_t)p,
+                                                     seed);
 }
 
 // K2: p_{k-1} = gamma xi, theta_new = theta + (gamma^2/2) grad_logpost + p_{k-1} (SMC1,
@@ -95,12 +102,17 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
     // (eqs. log_posterior, first_gradientlogposterior)
     double lp = 0.0;
     for (int p = 0; p < D; ++p) {
+      if (A.pr.kind[p] == 1) {  // uniform: flat inside the closed interval, zero outside
+        lp += (th[p] >= A.pr.mu[p] && th[p] <= A.pr.sd[p]) ? -log(A.pr.sd[p] - A.pr.mu[p])
+                                                           : kNegInf;
+        continue;
+      }
       const double z = (th[p] - A.pr.mu[p]) / A.pr.sd[p];
       lp += -kHalfLog2Pi - log(A.pr.sd[p]) - 0.5 * z * z;
       g[p] += -z / A.pr.sd[p];
     }
     const double ll = A.loglik[it];
-    const double lpost = lp + ll;
+    const double lpost = lp == kNegInf ? kNegInf : lp + ll;  // outside the support: zero
     A.logpost[it] = lpost;
     double v;
     if (A.first) {

@@ -47,7 +47,7 @@ namespace smc2 {
 
 struct PFArgs {
   const double *theta;  // [S][N][NP]
-  const double *y;      // [S][T_max][DX]
+  const double *y;      // [S][T_max][DY]
   double *loglik;       // [S][N]
   double *grad;         // [S][N][NP] or NULL
   const int32_t *T_len; // [S]
@@ -67,13 +67,14 @@ struct PFArgs {
   void *seg_buf;        // [slots][ckpt][rows][ld] (R): x before the step (DX rows), the noise
                         // (DX rows, only without `noise`), the normalised weight (1 row)
   void *noise;          // [slots][t_ld+1][DX][ld] (R) forward noise for the adjoint, or NULL
+  double mconst[4];     // model constants (the SIR model's N_pop, I_0, s_e^2, s_y)
 };
 
-// Dynamic shared memory of one item: y as R [lds_T * DX], then S_t (later max_t + log S_t) as
+// Dynamic shared memory of one item: y as R [lds_T * DY], then S_t (later max_t + log S_t) as
 // double [lds_T], then max_t as R [lds_T], then the flags as bytes [lds_T].
-template <typename R, int DX>
+template <typename R, int DY>
 __host__ __device__ constexpr size_t pf_dyn_lds_bytes(int lds_T) {
-  return ((size_t)lds_T * DX * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T * 8 +
+  return ((size_t)lds_T * DY * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T * 8 +
          ((size_t)lds_T * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T;
 }
 
@@ -107,8 +108,24 @@ __device__ __forceinline__ void filter_noise(int j0, uint32_t fid, uint32_t c3, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) e[p][4 * b + r] = z[r];
       }
+  } else if constexpr (DX == 2 && PPL % 2 == 0) {
+#pragma unroll
+    for (int b = 0; b < PPL / 2; ++b) {  // slots j0 + 2b and j0 + 2b + 1 share a block
+      R z[4];
+      normals4<R>((uint32_t)(j0 >> 1) + b, t, fid, c3, seed, z);
+      e[2 * b][0] = z[0];
+      e[2 * b][1] = z[1];
+      e[2 * b + 1][0] = z[2];
+      e[2 * b + 1][1] = z[3];
+    }
+  } else if constexpr (DX == 2) {
+    static_assert(PPL == 1, "two-component states take one or an even number of slots per lane");
+    R z[4];
+    normals4<R>((uint32_t)(j0 >> 1), t, fid, c3, seed, z);
+    e[0][0] = pick4(z, 2 * (j0 & 1));
+    e[0][1] = pick4(z, 2 * (j0 & 1) + 1);
   } else {
-    static_assert(DX == 1, "state dimension must be 1 or a multiple of 4");
+    static_assert(DX == 1, "state dimension must be 1, 2 or a multiple of 4");
     R z[4];  // fewer than four slots per thread: this thread's slots share one block
     normals4<R>((uint32_t)(j0 >> 2), t, fid, c3, seed, z);
 #pragma unroll
@@ -217,7 +234,7 @@ template <typename R, class Model, int WAVES, int PPL>
 __global__ __launch_bounds__(WAVES * 64,
                              (sizeof(R) == 4 && Model::DX == 1 && PPL <= 4 && WAVES <= 4) ? 4 : 1)
 void pf_fwd_adj_kernel(PFArgs A) {
-  constexpr int NT = WAVES * 64, MP = NT * PPL, DX = Model::DX, NP = Model::NP;
+  constexpr int NT = WAVES * 64, MP = NT * PPL, DX = Model::DX, DY = Model::DY, NP = Model::NP;
   constexpr double kNegInf = -__builtin_huge_val();
   // the reverse sweep loads step t - 1 while step t is processed; a multi-dimensional state
   // loads each step where it is used instead (its registers are the limit there)
@@ -231,7 +248,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
   __shared__ int sh_item;
   extern __shared__ double sh_dyn[];
   R *sh_y = (R *)sh_dyn;
-  double *sh_s = sh_dyn + ((size_t)A.lds_T * DX * sizeof(R) + 7) / 8;
+  double *sh_s = sh_dyn + ((size_t)A.lds_T * DY * sizeof(R) + 7) / 8;
   R *sh_mx = (R *)(sh_s + A.lds_T);
   uint8_t *sh_f = (uint8_t *)(sh_s + A.lds_T + ((size_t)A.lds_T * sizeof(R) + 7) / 8);
 
@@ -282,10 +299,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
       continue;
     }
     Model mdl;
-    mdl.setup(thv);
+    mdl.setup(thv, A.mconst);
     {
-      const double *ys = A.y + (size_t)s * A.T_max * DX;
-      for (int r = tid; r < T * DX; r += NT) sh_y[r] = (R)ys[r];
+      const double *ys = A.y + (size_t)s * A.T_max * DY;
+      for (int r = tid; r < T * DY; r += NT) sh_y[r] = (R)ys[r];
     }
 #pragma unroll
     for (int p = 0; p < PPL; ++p) sh_mark[j0 + p] = -1;
@@ -330,7 +347,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       }
       --ck_left;
       mdl.per_step(t);
-      const R *yv = sh_y + (size_t)(t - 1) * DX;
+      const R *yv = sh_y + (size_t)(t - 1) * DY;
       double mloc = kNegInf;
       {
         R e[PPL][DX];
@@ -488,7 +505,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
     // observation and transition are differentiated.  xp / xn: state before / after the step.
     auto reverse_step = [&](int t, const R (&xp)[PPL][DX], const R (&ce)[PPL][DX],
                             const R (&cw)[PPL], const int (&ca)[PPL]) {
-      const R *yv = sh_y + (size_t)(t - 1) * DX;
+      const R *yv = sh_y + (size_t)(t - 1) * DY;
       const bool res = t < T && sh_f[t - 1] != 0;
       if (t == T) {
 #pragma unroll
@@ -590,7 +607,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         if (kPrefetch && t > 1) load_trace(t - 1);
         if (!nz) filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, ce);
         mdl.per_step(t);
-        const R *yv = sh_y + (size_t)(t - 1) * DX;
+        const R *yv = sh_y + (size_t)(t - 1) * DY;
         const bool need_w = t == T || sh_f[t - 1] != 0;
         const R st = (R)sh_s[t - 1];  // max_t + log S_t
 #pragma unroll
@@ -638,7 +655,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
             filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
           }
           mdl.per_step(t);
-          const R *yv = sh_y + (size_t)(t - 1) * DX;
+          const R *yv = sh_y + (size_t)(t - 1) * DY;
           R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
           const R st = (R)sh_s[t - 1], mt = sh_mx[t - 1];  // max_t + log S_t, max_t
           R wv[PPL];

@@ -26,12 +26,12 @@ constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
 
 template <typename R, class Model, int W, int P>
 size_t dyn_lds_pf(int lds_T) {
-  return pf_dyn_lds_bytes<R, Model::DX>(lds_T);
+  return pf_dyn_lds_bytes<R, Model::DY>(lds_T);
 }
 
 template <typename R, class Model, int W, int P>
 void launch_pf(const PFArgs &a, int grid, hipStream_t st) {
-  const size_t dyn = pf_dyn_lds_bytes<R, Model::DX>(a.lds_T);
+  const size_t dyn = pf_dyn_lds_bytes<R, Model::DY>(a.lds_T);
   hipLaunchKernelGGL((pf_fwd_adj_kernel<R, Model, W, P>), dim3(grid), dim3(W * 64), dyn, st, a);
 }
 
@@ -87,10 +87,26 @@ void add_all_tiles_16d(std::vector<PFKernel> &v, int model, int precision) {
   add_entry<R, Model, 16, 2>(v, model, precision);
 }
 
+// Launch shapes for the two-component state (SIR): one particle per lane or an even number.
+template <typename R, class Model>
+void add_all_tiles_2d(std::vector<PFKernel> &v, int model, int precision) {
+  add_entry<R, Model, 1, 1>(v, model, precision);
+  add_entry<R, Model, 2, 1>(v, model, precision);
+  add_entry<R, Model, 1, 4>(v, model, precision);
+  add_entry<R, Model, 4, 1>(v, model, precision);
+  add_entry<R, Model, 2, 4>(v, model, precision);
+  add_entry<R, Model, 4, 2>(v, model, precision);
+  add_entry<R, Model, 4, 4>(v, model, precision);
+  add_entry<R, Model, 8, 2>(v, model, precision);
+  add_entry<R, Model, 8, 4>(v, model, precision);
+  add_entry<R, Model, 16, 2>(v, model, precision);
+}
+
 void register_lg1d(std::vector<PFKernel> &);
 void register_growth(std::vector<PFKernel> &);
 void register_sv(std::vector<PFKernel> &);
 void register_lgdiag(std::vector<PFKernel> &);
 void register_lg1dopt(std::vector<PFKernel> &);
+void register_sir(std::vector<PFKernel> &);
 
 }  // namespace smc2

@@ -41,6 +41,7 @@ const std::vector<PFKernel> &kernels() {
     register_sv(v);
     register_lgdiag(v);
     register_lg1dopt(v);
+    register_sir(v);
   });
   return v;
 }
@@ -51,10 +52,21 @@ int next_pow2(int v) {
   return p;
 }
 
+// SIR constants (N_pop, I_0, s_e^2, s_y): the paper's population, initial infections and noise
+// variance (Sec. IV-B) and an observation sd of 5
+constexpr double kSirDefaults[4] = {763.0, 1.0, 0.5, 5.0};
+
+// The model's constants as the kernels take them (zeros for a model without constants).
+void model_constants(const smc2_model *m, double out[4]) {
+  for (int i = 0; i < 4; ++i) out[i] = 0.0;
+  if (m->kind == SMC2_MODEL_SIR)
+    for (int i = 0; i < 4; ++i) out[i] = m->constants ? m->constants[i] : kSirDefaults[i];
+}
+
 bool model_ok(const smc2_model *m, std::string &why) {
   if (!m) return why = "model is NULL", false;
   if (!m->prior_mu || !m->prior_sd) return why = "model prior_mu/prior_sd is NULL", false;
-  if (m->d_y != m->d_x) return why = "d_y must equal d_x", false;
+  if (m->kind != SMC2_MODEL_SIR && m->d_y != m->d_x) return why = "d_y must equal d_x", false;
   switch (m->kind) {
     case SMC2_MODEL_LG1D:
       if (m->d_x != 1 || m->D != 3) return why = "LG1D needs d_x = 1, D = 3", false;
@@ -71,12 +83,35 @@ bool model_ok(const smc2_model *m, std::string &why) {
     case SMC2_MODEL_LG1D_OPT:
       if (m->d_x != 1 || m->D != 3) return why = "LG1D_OPT needs d_x = 1, D = 3", false;
       break;
+    case SMC2_MODEL_SIR: {
+      if (m->d_x != 2 || m->d_y != 1 || m->D != 2)
+        return why = "SIR needs d_x = 2, d_y = 1, D = 2", false;
+      double c[4];
+      model_constants(m, c);
+      for (double v : c)
+        if (!std::isfinite(v)) return why = "SIR constants must be finite", false;
+      if (!(c[0] > 0) || !(c[1] >= 0) || !(c[1] <= c[0]) || !(c[2] >= 0) || !(c[3] > 0))
+        return why = "SIR constants need N_pop > 0, 0 <= I_0 <= N_pop, s_e^2 >= 0, s_y > 0",
+               false;
+      break;
+    }
     default:
       return why = "unknown model kind", false;
   }
-  for (int p = 0; p < m->D; ++p)
-    if (!(m->prior_sd[p] > 0) || !std::isfinite(m->prior_mu[p]))
-      return why = "prior_sd must be > 0 and prior_mu finite", false;
+  for (int p = 0; p < m->D; ++p) {
+    const int kind = m->prior_kind ? m->prior_kind[p] : SMC2_PRIOR_NORMAL;
+    if (kind == SMC2_PRIOR_UNIFORM) {
+      if (!std::isfinite(m->prior_mu[p]) || !std::isfinite(m->prior_sd[p]) ||
+          !(m->prior_sd[p] > m->prior_mu[p]))
+        return why = "a uniform prior needs finite bounds with lower < upper", false;
+    } else if (kind == SMC2_PRIOR_NORMAL) {
+      if (!(m->prior_sd[p] > 0) || !std::isfinite(m->prior_sd[p]) ||
+          !std::isfinite(m->prior_mu[p]))
+        return why = "prior_sd must be finite and > 0 and prior_mu finite", false;
+    } else {
+      return why = "unknown prior kind", false;
+    }
+  }
   return true;
 }
 
@@ -85,6 +120,7 @@ Prior make_prior(const smc2_model *m) {
   for (int p = 0; p < m->D; ++p) {
     pr.mu[p] = m->prior_mu[p];
     pr.sd[p] = m->prior_sd[p];
+    pr.kind[p] = m->prior_kind ? m->prior_kind[p] : SMC2_PRIOR_NORMAL;
   }
   return pr;
 }
@@ -95,6 +131,17 @@ int default_tile(int MP, int dx, int precision) {
   // tile indices refer to kTiles; measured on MI355X (fused forward+adjoint, systematic
   // resampling at most steps): one or two waves with 4 to 8 particles per lane for the 1-D
   // models; the 16-dimensional state keeps one or two particles per lane
+  if (dx == 2) {  // the SIR model: one particle per lane up to 128, then four
+    switch (MP) {
+      case 64: return 1;     // {1, 1}
+      case 128: return 2;    // {2, 1}
+      case 256: return 3;    // {1, 4}
+      case 512: return 6;    // {2, 4}
+      case 1024: return 10;  // {4, 4}
+      case 2048: return 14;  // {8, 4}
+    }
+    return -1;
+  }
   if (dx == 16) {
     switch (MP) {
       case 64: return 1;     // {1, 1}
@@ -142,7 +189,8 @@ struct smc2_ctx {
   int num_cus = 256;
   bool reserved = false;
   smc2_model model{};
-  std::vector<double> prior_mu, prior_sd;
+  std::vector<double> prior_mu, prior_sd, constants;
+  std::vector<int32_t> prior_kind;
   smc2_pf_opts opts{};
   int S = 0, N = 0, M = 0, T_max = 0, tile = 0, T_max_hint = 1;
   Layout L{};
@@ -202,7 +250,7 @@ smc2_status check_opts(const smc2_pf_opts *o) {
 
 smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, int N, int M,
                            int T_max, int grid_slots, Layout &L) {
-  const int max_m = m->d_x == 16 ? 2048 : 4096;
+  const int max_m = m->d_x == 1 ? 4096 : 2048;
   if (M > max_m) return fail(SMC2_E_UNSUPPORTED, "M above the largest built tile");
   L.MP = next_pow2(M);
   const int Tc = std::max(T_max, 1);
@@ -363,6 +411,13 @@ smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_
   ctx->prior_sd.assign(model->prior_sd, model->prior_sd + model->D);
   ctx->model.prior_mu = ctx->prior_mu.data();
   ctx->model.prior_sd = ctx->prior_sd.data();
+  ctx->prior_kind.assign(model->D, SMC2_PRIOR_NORMAL);
+  if (model->prior_kind)
+    ctx->prior_kind.assign(model->prior_kind, model->prior_kind + model->D);
+  ctx->model.prior_kind = ctx->prior_kind.data();
+  ctx->constants.assign(4, 0.0);
+  model_constants(model, ctx->constants.data());
+  ctx->model.constants = ctx->constants.data();
   ctx->opts = *opts;
   ctx->S = S;
   ctx->N = N;
@@ -451,6 +506,7 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
   a.ckpt_buf = ctx->ckpt;
   a.seg_buf = ctx->seg;
   a.noise = (opts->want_grad && opts->store_noise) ? ctx->noise : nullptr;
+  model_constants(model, a.mconst);
   int grid = items;
   if (opts->persistent) {
     grid = std::min(items, std::min(ctx->L.slots, ctx->num_cus * k->occupancy(a.lds_T)));

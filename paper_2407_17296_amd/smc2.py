@@ -18,7 +18,8 @@ SMC2_OK, SMC2_E_INVALID_ARG, SMC2_E_UNSUPPORTED, SMC2_E_OUT_OF_MEMORY, SMC2_E_DE
     SMC2_E_NONFINITE = range(6)
 STATUS_NAMES = {0: "SMC2_OK", 1: "SMC2_E_INVALID_ARG", 2: "SMC2_E_UNSUPPORTED",
                 3: "SMC2_E_OUT_OF_MEMORY", 4: "SMC2_E_DEVICE", 5: "SMC2_E_NONFINITE"}
-LG1D, LG_DIAG, GROWTH, SV, LG1D_OPT = 0, 1, 2, 3, 4
+LG1D, LG_DIAG, GROWTH, SV, LG1D_OPT, SIR = 0, 1, 2, 3, 4, 5
+PRIOR_NORMAL, PRIOR_UNIFORM = 0, 1
 FP64, MIXED = 0, 1
 SYSTEMATIC, MULTINOMIAL = 0, 1
 
@@ -32,7 +33,9 @@ class SMC2Error(RuntimeError):
 class smc2_model(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("d_x", ctypes.c_int32), ("d_y", ctypes.c_int32),
                 ("D", ctypes.c_int32), ("prior_mu", ctypes.POINTER(ctypes.c_double)),
-                ("prior_sd", ctypes.POINTER(ctypes.c_double))]
+                ("prior_sd", ctypes.POINTER(ctypes.c_double)),
+                ("prior_kind", ctypes.POINTER(ctypes.c_int32)),
+                ("constants", ctypes.POINTER(ctypes.c_double))]
 
 
 class smc2_pf_opts(ctypes.Structure):
@@ -118,19 +121,30 @@ def _stream(stream=None):
 
 
 class Model:
-    """A smc2_model with its prior arrays kept alive."""
+    """A smc2_model with its prior and constant arrays kept alive.  d_y is 1 for the SIR model
+    and d_x otherwise; prior_kind (None: all normal) and constants (None: the model's defaults)
+    are passed through as given."""
 
-    def __init__(self, kind, d_x, D, prior_mu=None, prior_sd=None):
+    def __init__(self, kind, d_x, D, prior_mu=None, prior_sd=None, prior_kind=None,
+                 constants=None):
         self.kind, self.d_x, self.D = int(kind), int(d_x), int(D)
+        self.d_y = 1 if self.kind == SIR else self.d_x
         self.prior_mu = np.ascontiguousarray(np.zeros(D) if prior_mu is None else prior_mu, np.float64)
         self.prior_sd = np.ascontiguousarray(np.ones(D) if prior_sd is None else prior_sd, np.float64)
+        self.prior_kind = (None if prior_kind is None
+                           else np.ascontiguousarray(prior_kind, np.int32))
+        self.constants = None if constants is None else np.ascontiguousarray(constants, np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
-        self.c = smc2_model(self.kind, self.d_x, self.d_x, self.D,
-                            self.prior_mu.ctypes.data_as(dp), self.prior_sd.ctypes.data_as(dp))
+        ip = ctypes.POINTER(ctypes.c_int32)
+        self.c = smc2_model(self.kind, self.d_x, self.d_y, self.D,
+                            self.prior_mu.ctypes.data_as(dp), self.prior_sd.ctypes.data_as(dp),
+                            None if self.prior_kind is None else self.prior_kind.ctypes.data_as(ip),
+                            None if self.constants is None else self.constants.ctypes.data_as(dp))
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+        return cls(w.kind, w.d, w.D, w.prior_mu, w.prior_sd, getattr(w, "prior_kind", None),
+                   getattr(w, "constants", None))
 
 
 def pf_opts(precision=FP64, resampler=SYSTEMATIC, ess_frac=0.5, ckpt_interval=0, want_grad=1,

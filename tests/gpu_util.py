@@ -40,9 +40,13 @@ def gpu_pf(w, theta, precision=smc2.FP64, resampler=smc2.SYSTEMATIC, ess_frac=0.
     return out
 
 
+def oracle_model(oracle, w):
+    return oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd, w.prior_kind, w.constants)
+
+
 def oracle_pf(oracle, w, theta, s, i, k=1, resampler=smc2.SYSTEMATIC, ess_frac=0.5,
               want_trace=False):
-    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+    m = oracle_model(oracle, w)
     return oracle.pf(m, theta[s, i], w.y[s, :w.T_len[s]], w.M, w.seed, k, s * w.N + i,
                      resampler=resampler, ess_frac=ess_frac, want_trace=want_trace)
 
@@ -59,7 +63,7 @@ def oracle_sensitivity(oracle, w, theta, s, i, k, eps, resampler=0, ess_frac=0.5
     rng = np.random.default_rng(1000003 * s + i)
     dl = dg = 0.0
     same = True
-    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+    m = oracle_model(oracle, w)
     for _ in range(reps):
         u = rng.choice([-1.0, 1.0], size=w.D)
         th = theta[s, i] * (1.0 + eps * u)
@@ -84,5 +88,5 @@ def spread_theta(w, scale=0.5, seed=0):
     return w.theta_true + scale * rng.standard_normal((w.S, w.N, w.D))
 
 
-__all__ = ["say", "gpu_pf", "oracle_pf", "oracle_sensitivity", "rel_err", "spread_theta",
+__all__ = ["say", "gpu_pf", "oracle_model", "oracle_pf", "oracle_sensitivity", "rel_err", "spread_theta",
            "synth"]

@@ -109,3 +109,41 @@ def test_product_path_does_not_touch_the_oracle():
                 assert "pyoracle" not in src and "liboracle" not in src and "orc_" not in src, f
     code = open(os.path.join(pkg, "smc2.py")).read()
     assert "raise RuntimeError" in code and "not built" in code
+
+
+def test_sir_model_and_priors_are_validated(lib):
+    """The SIR model takes d_x = 2, d_y = 1, D = 2; its constants and uniform priors are
+    checked before anything is reserved."""
+    o = smc2.pf_opts()
+    ok = smc2.Model(smc2.SIR, 2, 2, [0.0, 0.0], [1.0, 1.0],
+                    prior_kind=[smc2.PRIOR_UNIFORM] * 2)
+    assert smc2.smc2_ctx_scratch_bytes(ok, o, 1, 64, 250, 35) > 0
+    with_c = smc2.Model(smc2.SIR, 2, 2, [0.0, 0.0], [1.0, 1.0],
+                        prior_kind=[smc2.PRIOR_UNIFORM] * 2, constants=[500.0, 5.0, 0.5, 2.0])
+    assert smc2.smc2_ctx_scratch_bytes(with_c, o, 1, 64, 250, 35) > 0
+    bad = [
+        smc2.Model(smc2.SIR, 1, 2),                                          # d_x
+        smc2.Model(smc2.SIR, 2, 2, constants=[100.0, 200.0, 0.5, 5.0]),      # I_0 > N_pop
+        smc2.Model(smc2.SIR, 2, 2, constants=[100.0, 1.0, -0.5, 5.0]),       # negative variance
+        smc2.Model(smc2.SIR, 2, 2, constants=[100.0, 1.0, 0.5, 0.0]),        # s_y = 0
+        smc2.Model(smc2.SIR, 2, 2, constants=[np.inf, 1.0, 0.5, 5.0]),       # non-finite
+        smc2.Model(smc2.SIR, 2, 2, [0.0, 1.0], [1.0, 1.0],
+                   prior_kind=[smc2.PRIOR_UNIFORM] * 2),                      # empty interval
+        smc2.Model(smc2.SIR, 2, 2, prior_kind=[0, 7]),                       # unknown kind
+    ]
+    for m in bad:
+        with pytest.raises(smc2.SMC2Error) as e:
+            smc2.smc2_ctx_scratch_bytes(m, o, 1, 64, 250, 35)
+        assert e.value.status == smc2.SMC2_E_INVALID_ARG
+    # two-component states are built up to 2048 particles
+    with pytest.raises(smc2.SMC2Error) as e:
+        smc2.smc2_ctx_scratch_bytes(ok, o, 1, 1, 4096, 35)
+    assert e.value.status == smc2.SMC2_E_UNSUPPORTED
+
+
+def test_sir_tiles_are_built(lib):
+    for t in (1, 2, 3, 4, 6, 7, 10, 11, 14, 17):
+        mp, w, p = smc2.smc2_tile_info(t, 2)
+        assert mp == 64 * w * p
+    with pytest.raises(smc2.SMC2Error):
+        smc2.smc2_tile_info(8, 2)  # 16 particles per lane is not built for two components

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _oracle_run(oracle, w, K, s=0):
-    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd, w.prior_kind, w.constants)
     return oracle.smc2_run(m, w.y[s, :w.T_len[s]], w.N, w.M, K, w.gamma, w.seed, series=s)
 
 
@@ -25,14 +25,21 @@ def _check_iteration(oracle, w, rec, k, s=0, pf_items=8):
     """Iteration k (0-based) of a recorded GPU run against the oracle's functions applied to the
     same inputs the GPU read: the move (k > 0), the filter at the GPU's theta, the prior and
     L-kernel weights, ESS, the resampling decision and the outer ancestors."""
-    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd)
+    m = oracle.Model(w.kind, w.d, w.D, w.prior_mu, w.prior_sd, w.prior_kind, w.constants)
     N, D, kk = w.N, w.D, k + 1
     lib = oracle.lib()
     th = rec.theta[k, s]
     if k == 0:
-        z = np.array([[lib.orc_normal(w.seed, 0xFFFFFFFF, s * N + i, oracle.c3(1, oracle.PRIOR_NORMAL), p)
+        c3p = oracle.c3(1, oracle.PRIOR_NORMAL)
+        z = np.array([[lib.orc_normal(w.seed, 0xFFFFFFFF, s * N + i, c3p, p)
                        for p in range(D)] for i in range(N)])
-        assert np.allclose(th, w.prior_mu + w.prior_sd * z, rtol=1e-14, atol=1e-14)
+        want = w.prior_mu + w.prior_sd * z
+        if w.prior_kind is not None:  # uniform parameters: uniform number p of the same stream
+            u = np.array([[lib.orc_uniform(w.seed, 0xFFFFFFFF, s * N + i, c3p, p)
+                           for p in range(D)] for i in range(N)])
+            want = np.where(np.asarray(w.prior_kind) == oracle.PRIOR_KIND_UNIFORM,
+                            w.prior_mu + (w.prior_sd - w.prior_mu) * u, want)
+        assert np.allclose(th, want, rtol=1e-14, atol=1e-14)
     else:
         for i in range(N):
             xi = [lib.orc_normal(w.seed, 0xFFFFFFFF, s * N + i, oracle.c3(kk, oracle.MOVE_NORMAL), p)
@@ -81,12 +88,15 @@ def _check_iteration(oracle, w, rec, k, s=0, pf_items=8):
     return res
 
 
-@pytest.mark.parametrize("index,kw,K", [(0, {}, 10), (3, dict(N=64, M=128, T=40), 6)])
+@pytest.mark.parametrize("index,kw,K", [(0, {}, 10), (3, dict(N=64, M=128, T=40), 6),
+                                        (5, {}, 15)])
 def test_fp64_smc2_iterations_match_oracle(oracle, index, kw, K):
     """Every iteration's move, filter and reweight/resample equal the oracle's on the GPU's own
-    inputs; the whole trajectory stays within rounding drift of the oracle's own run."""
+    inputs; the whole trajectory stays within rounding drift of the oracle's own run.  Index 5
+    is the SIR outbreak workload at the paper's sizes under its U(0, 1) priors."""
     w = synth.make(index, **kw)
-    w.prior_mu, w.prior_sd = (np.array(v, dtype=float) for v in PRIORS[index])
+    if index in PRIORS:
+        w.prior_mu, w.prior_sd = (np.array(v, dtype=float) for v in PRIORS[index])
     say("  smc2 %s N=%d M=%d K=%d" % (w.name, w.N, w.M, K))
     run, rec = driver.run_smc2(w, K=K, precision=smc2.FP64)
     recycled = run.recycled_estimate()
