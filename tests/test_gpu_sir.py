@@ -67,12 +67,39 @@ def test_fp64_sir_constants_and_outside_support(oracle):
 
 
 def test_mixed_sir_within_tolerance(oracle):
+    """Every filter whose ancestry matches the FP64 oracle's meets |d loglik| <= 1e-4 T and
+    gradient <= 1e-3.  The SIR log-weights are large (squared residuals of counts in the
+    hundreds), so their FP32 rounding moves cumulative weights by ~1e-5 relative and a filter
+    meets an ancestor flip with a probability of a few percent per resampling; after one the two
+    particle systems differ by Monte Carlo noise (reported; the estimator is checked
+    statistically below)."""
     w = _sir(N=32)
     theta = spread_theta(w, 0.05, seed=42)
     items = [(0, i) for i in range(w.N)]
     ll, g, tr = gpu_pf(w, theta, precision=smc2.MIXED, k=2, trace_items=items)
-    n_ok, _ = _mixed_report(oracle, w, theta, ll, g, tr, 2, items, w.name)
-    assert n_ok >= 0.9 * len(items)
+    _, rows = _mixed_report(oracle, w, theta, ll, g, tr, 2, items, w.name)
+    same = [r for r in rows if r[6] == 0]
+    say("  %d / %d filters keep the FP64 ancestry throughout" % (len(same), len(rows)))
+    assert len(same) >= len(rows) // 2
+    assert all(r[2] for r in same)
+
+
+def test_mixed_and_fp64_sir_estimate_the_same_likelihood():
+    """N independent filters at the data-generating rates: the paired differences of loglik and
+    gradient between the mixed and the FP64 form have mean zero within 4 standard errors."""
+    w = _sir(N=512)
+    theta = np.broadcast_to(w.theta_true, (1, w.N, w.D)).copy()
+    l64, g64, _ = gpu_pf(w, theta, precision=smc2.FP64, k=7)
+    l32, g32, _ = gpu_pf(w, theta, precision=smc2.MIXED, k=7)
+    d = (l32 - l64)[0]
+    se = d.std(ddof=1) / np.sqrt(len(d))
+    dg = (g32 - g64)[0]
+    seg = dg.std(axis=0, ddof=1) / np.sqrt(len(d))
+    say("  SIR loglik mean fp64 %.4f (sd %.3f); paired diff %.2e +- %.2e; grad diff %s +- %s" % (
+        l64.mean(), l64.std(), d.mean(), se, np.array2string(dg.mean(axis=0), precision=3),
+        np.array2string(seg, precision=3)))
+    assert abs(d.mean()) <= 4 * se + 1e-9
+    assert np.all(np.abs(dg.mean(axis=0)) <= 4 * seg + 1e-9)
 
 
 def test_sir_stored_and_regenerated_noise_agree():
