@@ -233,6 +233,26 @@ __device__ __forceinline__ double wave_max(double v) {
               fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
+// The FP32 maximum over a wave (exact, like any maximum: converting it to FP64 afterwards gives
+// the FP64 maximum of the converted values).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v), __float_as_int(v)));
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  v = fmaxf(v, dpp_f32<kDppQuadXor1>(v));
+  v = fmaxf(v, dpp_f32<kDppQuadXor2>(v));
+  v = fmaxf(v, dpp_f32<kDppRowHalfMirror>(v));
+  v = fmaxf(v, dpp_f32<kDppRowMirror>(v));
+  return fmaxf(fmaxf(readlane_f32(v, 0), readlane_f32(v, 16)),
+               fmaxf(readlane_f32(v, 32), readlane_f32(v, 48)));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_f64<kDppQuadXor1>(0.0, v);
   v += dpp_f64<kDppQuadXor2>(0.0, v);

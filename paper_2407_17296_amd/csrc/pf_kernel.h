@@ -348,7 +348,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       --ck_left;
       mdl.per_step(t);
       const R *yv = sh_y + (size_t)(t - 1) * DY;
-      double mloc = kNegInf;
+      R mloc = (R)kNegInf;  // a maximum is exact in R; it widens to FP64 unchanged
       {
         R e[PPL][DX];
         filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
@@ -358,13 +358,13 @@ void pf_fwd_adj_kernel(PFArgs A) {
           R v = lW[p] + mdl.advance(x[p], e[p], yv);  // lW now holds the unnormalised lw
           if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
           lW[p] = v;
-          mloc = fmax(mloc, (double)v);
+          mloc = fmax(mloc, v);
         }
       }
       // log-sum-exp, exchange 1: the maximum
       double *ex = sh_ex[t & 1];
       {
-        const double mw = wave_max(mloc);
+        const double mw = (double)wave_max(mloc);
         if (lane == 0) ex[wid] = mw;
       }
       __syncthreads();
@@ -375,21 +375,22 @@ void pf_fwd_adj_kernel(PFArgs A) {
         dead = true;
         break;
       }
-      // exchange 2: FP64 sums of exp(lw - max) (as a lane prefix scan) and of their squares
+      // exchange 2: FP64 sums of exp(lw - max) (as a lane prefix scan) and of their squares (a
+      // lane's few squares summed in R: they only decide whether to resample)
       const R mxR = (R)mx;
       R ew[PPL];
-      double acc = 0.0, qacc = 0.0;
+      double acc = 0.0;
+      R qacc = (R)0;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         ew[p] = fexp(lW[p] - mxR);
-        const double ed = (double)ew[p];
-        acc += ed;
-        qacc += ed * ed;
+        acc += (double)ew[p];
+        qacc += ew[p] * ew[p];
         lW[p] = lW[p] - mxR;  // the carry: log-weights shifted by the maximum
       }
       const double inc = wave_inclusive_sum(acc);
       {
-        const double sw = readlane_f64(inc, 63), qw = wave_sum(qacc);
+        const double sw = readlane_f64(inc, 63), qw = wave_sum((double)qacc);
         if (lane == 0) {
           ex[WAVES + 2 * wid] = sw;
           ex[WAVES + 2 * wid + 1] = qw;
