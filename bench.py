@@ -31,8 +31,8 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TSLOTS = 256 * 128 * 2.4e9 / 1e12  # T FP32 lane-slots per second
 
 # Algorithmic VALU work per particle-step of the CRN-PF forward sweep and its adjoint for d = 1,
-# in FP32 lane-slots of a direct implementation of the method's arithmetic (itemised in
-# the design doc).  An FP32 add / multiply / FMA / compare / select / integer op takes one slot; an
+# in FP32 lane-slots of a direct implementation of the method's arithmetic (itemised
+# below).  An FP32 add / multiply / FMA / compare / select / integer op takes one slot; an
 # FP64 operation two (half rate); the 32 x 32 -> 64-bit integer multiply-add and the
 # transcendental unit (log, sqrt, sin, cos, exp) four (quarter rate).  The rates were measured
 # on the device with dependent-chain-free loops.
@@ -40,8 +40,8 @@ PEAK_VALU_TSLOTS = 256 * 128 * 2.4e9 / 1e12  # T FP32 lane-slots per second
 #              + 4 xors) / 4 = 30; half a Box-Muller pair: (8 full + 4 transcendental x 4)
 #              / 2 = 12                                                           -> 42
 #   model      transition 2, log g 4, weight update and guard 3                   ->  9
-#   normalise  FP64 running max 4, subtract / scale / exp 6, FP64 conversion and the two sums
-#              6, shifted carry 1                                                 -> 17
+#   normalise  running max 1 (exact in FP32), subtract / scale / exp 6, FP64 conversion and
+#              FP64 sum 4, squared sum for the ESS test 1, shifted carry 1        -> 13
 #   resample   per resampled step: FP64 prefix 4, offspring count from P / tot 24, marker
 #              and gather 2                                                       -> 30 r
 #   adjoint    transposed derivatives of log g and of the transition 11, summed into the
@@ -49,7 +49,7 @@ PEAK_VALU_TSLOTS = 256 * 128 * 2.4e9 / 1e12  # T FP32 lane-slots per second
 #                                                                                 -> 14 + 2 r
 # Rebuilding the step in the adjoint (from checkpoints) is implementation work, not counted.
 def alg_slots_per_particle_step(M, r):
-    noise, model, normalise = 42.0, 9.0, 17.0
+    noise, model, normalise = 42.0, 9.0, 13.0
     forward = noise + model + normalise + 30.0 * r
     adjoint = 14.0 + 2.0 * r
     return forward + adjoint
