@@ -11,8 +11,9 @@ namespace smc2 {
 constexpr int kMaxD = 32;
 
 // Independent priors: kind 0 N(mu, sd^2); kind 1 uniform on [mu, sd] (lower, upper bound).
+// lnorm: log sd (normal) or log(upper - lower) (uniform), formed on the host.
 struct Prior {
-  double mu[kMaxD], sd[kMaxD];
+  double mu[kMaxD], sd[kMaxD], lnorm[kMaxD];
   int kind[kMaxD];
 };
 
@@ -70,9 +71,10 @@ struct OuterArgs {
   int32_t *status;
 };
 
-// K3: one workgroup of OUTER_THREADS threads per series; each thread owns a contiguous block of
-// samples (N <= 4096).
-constexpr int kOuterThreads = 512;
+// K3: one workgroup of kOuterThreads threads per series (N <= 4096); sample i belongs to thread
+// i mod kOuterThreads in round i / kOuterThreads, so a wave's loads and stores of the population
+// are consecutive samples.
+constexpr int kOuterThreads = 1024;
 constexpr int kOuterMaxN = 4096;
 constexpr int kOuterPer = kOuterMaxN / kOuterThreads;
 
@@ -81,11 +83,10 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
   constexpr double kNegInf = -__builtin_huge_val();
   __shared__ double sh_P[kOuterMaxN];
   __shared__ double sh_red[2][2 * WAVES + 2];
+  __shared__ double sh_scan[2][WAVES];
   __shared__ double sh_est[WAVES][2 * kMaxD];
   const int s = blockIdx.x, tid = threadIdx.x;
   const int N = A.N, D = A.D;
-  const int per = (N + kOuterThreads - 1) / kOuterThreads;
-  const int i0 = tid * per;
   const uint32_t k = *A.iteration;
   const double g2 = A.gamma * A.gamma;
 
@@ -93,8 +94,8 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
   double mloc = kNegInf;
   for (int r = 0; r < kOuterPer; ++r) {
     lw[r] = kNegInf;
-    const int i = i0 + r;
-    if (r >= per || i >= N) continue;
+    const int i = r * kOuterThreads + tid;
+    if (i >= N) continue;
     const size_t it = (size_t)s * N + i;
     double *th = A.theta + it * D;
     double *g = A.grad_logpost + it * D;
@@ -103,12 +104,11 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
     double lp = 0.0;
     for (int p = 0; p < D; ++p) {
       if (A.pr.kind[p] == 1) {  // uniform: flat inside the closed interval, zero outside
-        lp += (th[p] >= A.pr.mu[p] && th[p] <= A.pr.sd[p]) ? -log(A.pr.sd[p] - A.pr.mu[p])
-                                                           : kNegInf;
+        lp += (th[p] >= A.pr.mu[p] && th[p] <= A.pr.sd[p]) ? -A.pr.lnorm[p] : kNegInf;
         continue;
       }
       const double z = (th[p] - A.pr.mu[p]) / A.pr.sd[p];
-      lp += -kHalfLog2Pi - log(A.pr.sd[p]) - 0.5 * z * z;
+      lp += -kHalfLog2Pi - A.pr.lnorm[p] - 0.5 * z * z;
       g[p] += -z / A.pr.sd[p];
     }
     const double ll = A.loglik[it];
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
     mloc = fmax(mloc, v);
   }
   const double mx = block_max<WAVES>(mloc, sh_red[0]);
-  double e[kOuterPer], S = 0.0, Q = 0.0;
+  double e[kOuterPer], S = 0.0, Q = 0.0;  // e = 0 past N (lw = -inf there)
   for (int r = 0; r < kOuterPer; ++r) {
     e[r] = (mx == kNegInf) ? 0.0 : exp(lw[r] - mx);
     S += e[r];
@@ -157,8 +157,8 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
     const int lane = tid & 63, wid = tid >> 6;
     for (int p = 0; p < D; ++p) {
       double m1 = 0.0, m2 = 0.0;
-      for (int r = 0; r < per; ++r) {
-        const int i = i0 + r;
+      for (int r = 0; r < kOuterPer; ++r) {
+        const int i = r * kOuterThreads + tid;
         if (i >= N || !(e[r] > 0.0)) continue;  // zero-weight samples take no part
         const double v = A.theta[((size_t)s * N + i) * D + p];
         m1 += e[r] * v;
@@ -188,27 +188,30 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
   }
   if (!res) {
     if (A.anc_out)
-      for (int r = 0; r < per; ++r)
-        if (i0 + r < N) A.anc_out[(size_t)s * N + i0 + r] = i0 + r;
+      for (int r = 0; r < kOuterPer; ++r) {
+        const int i = r * kOuterThreads + tid;
+        if (i < N) A.anc_out[(size_t)s * N + i] = i;
+      }
     return;
   }
-  // systematic resampling: inclusive FP64 prefix, lower bound of (i + nu)/N * total
-  double acc = 0.0, pre[kOuterPer];
-  for (int r = 0; r < kOuterPer; ++r) {
-    acc += e[r];
-    pre[r] = acc;
+  // systematic resampling: inclusive FP64 prefix in sample order (one workgroup scan per
+  // round, carried across rounds; the scans alternate two buffers), lower bound of
+  // (i + nu)/N * total
+  double carry = 0.0;
+  for (int r = 0; r * kOuterThreads < N; ++r) {
+    double tot;
+    const double exc = block_exclusive_scan<WAVES>(e[r], sh_scan[r & 1], tot);
+    const int i = r * kOuterThreads + tid;
+    if (i < N) sh_P[i] = carry + (exc + e[r]);
+    carry += tot;
   }
-  double tot;
-  const double off = block_exclusive_scan<WAVES>(acc, sh_red[0], tot);
-  for (int r = 0; r < per; ++r)
-    if (i0 + r < N) sh_P[i0 + r] = off + pre[r];
   const double nu = uniform_m(kNoSlot, (uint32_t)s, stream_word(k, kStreamOuter), 0u, A.seed);
   __syncthreads();
   const double total = sh_P[N - 1];
   const double lse = mx + log(S);
   const int W = 2 * D + 2;
-  for (int r = 0; r < per; ++r) {
-    const int i = i0 + r;
+  for (int r = 0; r < kOuterPer; ++r) {
+    const int i = r * kOuterThreads + tid;
     if (i >= N) continue;
     const int a = min(lower_bound_lds(sh_P, N, ((double)i + nu) / (double)N * total), N - 1);
     if (A.anc_out) A.anc_out[(size_t)s * N + i] = a;
@@ -222,8 +225,8 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
     sc[2 * D + 1] = A.loglik[src];
   }
   __syncthreads();  // every read of the old population precedes the in-place writes
-  for (int r = 0; r < per; ++r) {
-    const int i = i0 + r;
+  for (int r = 0; r < kOuterPer; ++r) {
+    const int i = r * kOuterThreads + tid;
     if (i >= N) continue;
     const size_t dst = (size_t)s * N + i;
     const double *sc = A.scratch + dst * W;

@@ -121,6 +121,8 @@ Prior make_prior(const smc2_model *m) {
     pr.mu[p] = m->prior_mu[p];
     pr.sd[p] = m->prior_sd[p];
     pr.kind[p] = m->prior_kind ? m->prior_kind[p] : SMC2_PRIOR_NORMAL;
+    pr.lnorm[p] = pr.kind[p] == SMC2_PRIOR_UNIFORM ? std::log(pr.sd[p] - pr.mu[p])
+                                                   : std::log(pr.sd[p]);
   }
   return pr;
 }
