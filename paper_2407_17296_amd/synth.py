@@ -25,9 +25,11 @@ gamma; Sec. II and Sec. III) at the sizes of the project's benchmark table:
               M = 250, K = 15: the paper's outbreak experiment with simulated data in place of
               its outbreak record
 
-Workloads 0-4 sample parameters in unconstrained coordinates (log of scales, atanh of phi) under
-an independent N(0, 1) prior; workload 5 samples (beta, gamma) on their natural scale under the
-paper's independent U(0, 1) priors.  data_seed = 20240724 + i, run seed = 17296 + i.
+Workloads 0, 1, 3 and 4 sample parameters in unconstrained coordinates (log of scales, atanh of
+phi) under an independent N(0, 1) prior; workload 2 puts N(0.725, 0.13^2) (the centre and the
+spread of U(0.5, 0.95)) on each transition entry and N(0, 1) on the log scales, since entries of
+N(0, 1) draws beyond one make a 16-dimensional state explode within T = 100 steps; workload 5
+samples (beta, gamma) on their natural scale under the paper's independent U(0, 1) priors.  data_seed = 20240724 + i, run seed = 17296 + i.
 """
 from dataclasses import dataclass, field
 
@@ -163,6 +165,9 @@ def make(index, N=None, M=None, K=None, S=None, T=None):
     for s in range(Ss):
         y[s, :T_len[s]] = _simulate(kind, th, int(T_len[s]), dy, rng)
     extra = {}
+    if kind == LG_DIAG:  # a prior on the transition entries that keeps the dynamics stable
+        extra = dict(prior_mu=np.concatenate([np.full(d, 0.725), np.zeros(2)]),
+                     prior_sd=np.concatenate([np.full(d, 0.13), np.ones(2)]))
     if kind == SIR:  # U(0, 1) priors: the bounds ride in prior_mu / prior_sd
         extra = dict(prior_mu=np.zeros(D), prior_sd=np.ones(D), dy=1,
                      prior_kind=np.full(D, PRIOR_KIND_UNIFORM, dtype=np.int32),

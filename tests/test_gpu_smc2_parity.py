@@ -191,3 +191,17 @@ def test_step_size_pilot_picks_the_best_mean_ess():
     say("  pilot mean ESS / N: %s -> gamma %.3f" % (scores, best))
     assert best in scores and scores[best] == max(scores.values())
     assert all(0.0 < v <= 1.0 for v in scores.values())
+
+
+@pytest.mark.parametrize("N", [1500, 4096])
+def test_outer_step_at_large_and_ragged_population(oracle, N):
+    """The reweighting kernel at its largest population (4096 samples: four full rounds of its
+    1024 threads) and at a ragged one (1500: a partial second round), iteration by iteration
+    against the oracle's functions on the GPU's own inputs."""
+    w = synth.make(3, N=N, M=64, T=20)
+    w.prior_mu, w.prior_sd = (np.array(v, dtype=float) for v in PRIORS[3])
+    K = 3
+    run, rec = driver.run_smc2(w, K=K, precision=smc2.FP64)
+    run.close()
+    resampled = [k + 1 for k in range(K) if _check_iteration(oracle, w, rec, k, pf_items=4)]
+    say("  N=%d: %d iterations match; resampled at %s" % (N, K, resampled))
