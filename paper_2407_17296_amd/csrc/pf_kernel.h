@@ -133,6 +133,21 @@ __device__ __forceinline__ void filter_noise(int j0, uint32_t fid, uint32_t c3, 
   }
 }
 
+// The noise of one slot j of step t when the state dimension is a multiple of four (the same
+// numbers as filter_noise: blocks j * DX/4 .. j * DX/4 + DX/4 - 1).
+template <typename R, int DX>
+__device__ __forceinline__ void particle_noise(int j, uint32_t fid, uint32_t c3, uint32_t t,
+                                               uint64_t seed, R (&e)[DX]) {
+  static_assert(DX % 4 == 0, "one slot's noise fills whole Philox blocks");
+#pragma unroll
+  for (int b = 0; b < DX / 4; ++b) {
+    R z[4];
+    normals4<R>((uint32_t)(j * (DX / 4) + b), t, fid, c3, seed, z);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) e[4 * b + r] = z[r];
+  }
+}
+
 // Multinomial resampling uniforms of step t for offspring slots j0 .. j0 + PPL - 1: word i % 4
 // of block (i / 4, t).
 template <int PPL>
@@ -239,11 +254,16 @@ void pf_fwd_adj_kernel(PFArgs A) {
   // the reverse sweep loads step t - 1 while step t is processed; a multi-dimensional state
   // loads each step where it is used instead (its registers are the limit there)
   constexpr bool kPrefetch = DX == 1;
+  // Wide states (a multiple of four components) stream one particle at a time through each
+  // step, so that a lane holds only its particles' states and adjoints across steps, and sum the
+  // parameter adjoint per wave into LDS instead of keeping NP FP64 accumulators per lane.
+  constexpr bool kWide = DX % 4 == 0;
   __shared__ double sh_P[MP];        // multinomial prefix
   __shared__ R sh_X[2][MP];          // gather / adjoint-scatter staging (ping-pong)
   __shared__ int sh_mark[MP + 64];   // systematic first-offspring markers + a dummy per lane
   __shared__ double sh_ex[2][3 * WAVES];  // per-wave max and (sum, sum of squares), ping-pong
   __shared__ double sh_vec[WAVES * NP];
+  __shared__ double sh_tb[kWide ? WAVES * NP : 1];  // per-wave parameter adjoint (wide states)
   __shared__ int sh_imax[WAVES];
   __shared__ int sh_item;
   extern __shared__ double sh_dyn[];
@@ -349,7 +369,20 @@ void pf_fwd_adj_kernel(PFArgs A) {
       mdl.per_step(t);
       const R *yv = sh_y + (size_t)(t - 1) * DY;
       R mloc = (R)kNegInf;  // a maximum is exact in R; it widens to FP64 unchanged
-      {
+      if constexpr (kWide) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          R ep[DX];
+          particle_noise<R, DX>(j0 + p, fid, c3s, (uint32_t)t, seed, ep);
+          if (nz)
+#pragma unroll
+            for (int q = 0; q < DX; ++q) nz[((size_t)t * DX + q) * LD + j0 + p] = ep[q];
+          R v = lW[p] + mdl.advance(x[p], ep, yv);  // lW now holds the unnormalised lw
+          if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
+          lW[p] = v;
+          mloc = fmax(mloc, v);
+        }
+      } else {
         R e[PPL][DX];
         filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
         if (nz) store_noise(t, e);
@@ -500,7 +533,52 @@ void pf_fwd_adj_kernel(PFArgs A) {
     }
 #pragma unroll
     for (int p = 0; p < NP; ++p) tb[p] = 0.0;
+    if (kWide && lane == 0)
+      for (int k = 0; k < NP; ++k) sh_tb[wid * NP + k] = 0.0;
     int pp = 0;  // ping-pong selector of the gather / scatter staging in sh_X
+    // offspring -> parent: xb_pre[m] = sum over offspring i with a_i = m of xb_post[i]; a lane
+    // adds each run of its offspring that share a parent once.  The staging is zero before use
+    // and each reader zeroes what it read.
+    auto scatter_to_parents = [&](const int (&ca)[PPL]) {
+#pragma unroll
+      for (int q = 0; q < DX; ++q) {
+        R *ss = sh_X[pp];
+        pp ^= 1;
+        int ra = ca[0];
+        R rs = (R)0;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          const R v = (j0 + p < M) ? xb[p][q] : (R)0;
+          if (ca[p] != ra) {
+            if (rs != (R)0) atomicAdd(&ss[ra], rs);
+            ra = ca[p];
+            rs = (R)0;
+          }
+          rs += v;
+        }
+        if (rs != (R)0) atomicAdd(&ss[ra], rs);
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          xb[p][q] = ss[j0 + p];
+          ss[j0 + p] = (R)0;
+        }
+      }
+    };
+    // a step's parameter adjoint (the lane's particles summed in R) joins the FP64 accumulator:
+    // per lane, or for wide states per wave in LDS
+    auto add_step_adjoint = [&](const R (&tp)[NP]) {
+      if constexpr (kWide) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          const double sk = wave_sum((double)tp[k]);
+          if (lane == 0) sh_tb[wid * NP + k] += sk;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) tb[k] += (double)tp[k];
+      }
+    };
     // One reverse step t: the weight adjoint restarts at resampled steps and at T, the state
     // adjoint is scatter-added from offspring to parents at resampled steps, then the step's
     // observation and transition are differentiated.  xp / xn: state before / after the step.
@@ -512,33 +590,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
       } else if (res) {
-        // offspring -> parent: xb_pre[m] = sum over offspring i with a_i = m of xb_post[i];
-        // a lane adds each run of its offspring that share a parent once.  The staging is
-        // zero before use and each reader zeroes what it read.
-#pragma unroll
-        for (int q = 0; q < DX; ++q) {
-          R *ss = sh_X[pp];
-          pp ^= 1;
-          int ra = ca[0];
-          R rs = (R)0;
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) {
-            const R v = (j0 + p < M) ? xb[p][q] : (R)0;
-            if (ca[p] != ra) {
-              if (rs != (R)0) atomicAdd(&ss[ra], rs);
-              ra = ca[p];
-              rs = (R)0;
-            }
-            rs += v;
-          }
-          if (rs != (R)0) atomicAdd(&ss[ra], rs);
-          __syncthreads();
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) {
-            xb[p][q] = ss[j0 + p];
-            ss[j0 + p] = (R)0;
-          }
-        }
+        scatter_to_parents(ca);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
       }
@@ -555,8 +607,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         (void)mdl.advance(xn, ce[p], yv);
         mdl.advance_adj(yv, xp[p], xn, ce[p], wb[p], xb[p], tp);
       }
-#pragma unroll
-      for (int k = 0; k < NP; ++k) tb[k] += (double)tp[k];
+      add_step_adjoint(tp);
     };
     auto zero_staging = [&]() {
       __syncthreads();  // earlier readers of the staging are done
@@ -573,6 +624,50 @@ void pf_fwd_adj_kernel(PFArgs A) {
       // Every step's starting state (x, log W) is a checkpoint: one reverse sweep that reads
       // the state before each step, rebuilds the step and its weight, and differentiates it.
       zero_staging();
+      if constexpr (kWide) {
+        // one particle at a time: its state before the step (checkpoint) and noise are read,
+        // the step and its weight rebuilt, and the step differentiated
+        for (int t = T; t >= 1; --t) {
+          const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
+          const bool res = t < T && sh_f[t - 1] != 0;
+          const bool need_w = t == T || res;
+          R cl[PPL];
+          int ca[PPL];
+          load_run<PPL>(cks + DX * LD + j0, cl);
+          if (res) {
+            load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, ca);
+            scatter_to_parents(ca);
+          }
+          mdl.per_step(t);
+          const R *yv = sh_y + (size_t)(t - 1) * DY;
+          const R st = (R)sh_s[t - 1];  // max_t + log S_t
+          R tp[NP];
+#pragma unroll
+          for (int k = 0; k < NP; ++k) tp[k] = (R)0;
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            R xp[DX], ep[DX], xn[DX];
+#pragma unroll
+            for (int q = 0; q < DX; ++q) xp[q] = cks[q * LD + j0 + p];
+            if (nz) {
+#pragma unroll
+              for (int q = 0; q < DX; ++q) ep[q] = nz[((size_t)t * DX + q) * LD + j0 + p];
+            } else {
+              particle_noise<R, DX>(j0 + p, fid, c3s, (uint32_t)t, seed, ep);
+            }
+#pragma unroll
+            for (int q = 0; q < DX; ++q) xn[q] = xp[q];
+            const R lam = mdl.advance(xn, ep, yv);
+            if (need_w) {  // the weight adjoint restarts: the normalised weight of the step
+              R v = cl[p] + lam;
+              if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
+              wb[p] = fexp(v - st);
+            }
+            mdl.advance_adj(yv, xp, xn, ep, wb[p], xb[p], tp);
+          }
+          add_step_adjoint(tp);
+        }
+      } else {
       R nx[PPL][DX], nl[PPL], ne[PPL][DX];
       int na[PPL];
       auto load_trace = [&](int t) {
@@ -624,6 +719,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
         }
         reverse_step(t, cx, ce, cw, ca);
+      }
       }
     } else {
       // segment rows of one step: x before the step (DX rows), the noise when it is not
@@ -747,7 +843,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
       for (int p = 0; p < PPL; ++p) mdl.init_adj(e[p], xb[p], tb);
     }
-    block_sum_vec<WAVES, NP>(tb, sh_vec);
+    block_sum_vec<WAVES, NP>(tb, sh_vec);  // its barriers also publish sh_tb
+    if constexpr (kWide) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+        for (int w = 0; w < WAVES; ++w) tb[k] += sh_tb[w * NP + k];
+    }
     if (tid < NP) {
       double v = tb[0];
 #pragma unroll
