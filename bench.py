@@ -57,9 +57,10 @@ def alg_slots_per_particle_step(M, r):
 
 def algorithmic_bytes_per_particle_step(r, c, rs, d=1):
     """HBM bytes the method must move per particle-step: the int32 ancestor written in the
-    forward and read in the adjoint at a resampled step (fraction r), and the (x, log W)
-    checkpoint written and read once every c steps (rs bytes per value)."""
-    return r * 8.0 + 2.0 * (d + 1) * rs / c
+    forward and read in the adjoint at a resampled step (fraction r), and the checkpoint written
+    and read once every c steps (rs bytes per value): the state, and the carried log-weight
+    unless the step before resampled (then every log-weight is -log M and none is stored)."""
+    return r * 8.0 + 2.0 * (d + 1.0 - r) * rs / c
 
 
 def design_bytes_per_particle_step(r, c, rs, store_noise, d=1):

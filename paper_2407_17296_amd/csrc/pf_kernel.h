@@ -356,12 +356,16 @@ void pf_fwd_adj_kernel(PFArgs A) {
     bool dead = false;
     int nres = 0;
     int ck_left = 0, ck_idx = 0;
+    // the carried log-weights are all -log M at the start and right after a resampling step:
+    // a checkpoint then stores the state only, and the adjoint takes the constant (not for wide
+    // states, whose checkpoints are mostly state and whose registers are scarce)
+    bool lw_uniform = !kWide;
     for (int t = 1; t <= T; ++t) {
       if (ck_left == 0) {
         R *cks = ck + (size_t)ck_idx * (DX + 1) * LD;
 #pragma unroll
         for (int q = 0; q < DX; ++q) store_comp<PPL>(cks + q * LD + j0, x, q);
-        store_run<PPL>(cks + DX * LD + j0, lW);
+        if (!lw_uniform) store_run<PPL>(cks + DX * LD + j0, lW);
         ck_left = c;
         ++ck_idx;
       }
@@ -438,6 +442,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         Q = Q + ex[WAVES + 2 * w + 1];
       }
       const bool res = (t < T) && (S * S < A.ess_thresh * Q);  // ESS = S^2 / Q (eq. ess)
+      lw_uniform = res && !kWide;
       if (tid == 0) {
         sh_s[t - 1] = S;
         sh_mx[t - 1] = mxR;
@@ -678,7 +683,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
           load_comp<PPL>(cks + q * LD + j0, nx, q);
           if (nz) load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ne, q);
         }
-        load_run<PPL>(cks + DX * LD + j0, nl);
+        if (t > 1 && sh_f[t - 2] == 0)
+          load_run<PPL>(cks + DX * LD + j0, nl);
+        else
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) nl[p] = lWeqR;
         if (lres)
           load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, na);
         else
@@ -733,7 +742,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
         const R *cks = ck + (size_t)seg * (DX + 1) * LD;
 #pragma unroll
         for (int q = 0; q < DX; ++q) load_comp<PPL>(cks + q * LD + j0, x, q);
-        load_run<PPL>(cks + DX * LD + j0, lW);
+        if (kWide || (t0 > 0 && sh_f[t0 - 1] == 0))
+          load_run<PPL>(cks + DX * LD + j0, lW);
+        else
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
         // recompute the segment with the stored ancestors and log normalisers
         R ne[PPL][DX];
         if (nz) load_noise(t0 + 1, ne);
