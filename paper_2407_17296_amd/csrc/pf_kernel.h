@@ -9,7 +9,8 @@
 // weights, and offspring i takes the first parent m with P_m >= u_i P_{M-1} (the paper's index
 // kappa_i = sum_j [nu_i > c_j]), with systematic u_i = (i + nu)/M or multinomial u_i = nu_i;
 // equal weights after.  The int32 ancestors are stored, and (x, log W) checkpoints are stored
-// every c steps.
+// every c steps (log W only where the step before did not resample: after a resampling step
+// every log-weight is -log M, which the adjoint takes from the step's flag).
 //
 // The log-sum-exp takes two workgroup exchanges per step: the maximum, then the FP64 sums of
 // exp(lw - max) (the total of a lane prefix scan that resampling reuses) and of their squares.
@@ -27,14 +28,18 @@
 //
 // Adjoint (the transpose of App. A's tangent recursion, eqs. dloglik..dxk, with App. B's rules
 // that resampled weights have zero derivative and a resampled particle inherits its parent's):
-// segments are processed last to first; each is recomputed forward from its checkpoint with the
-// stored ancestors and stored s_t into a segment buffer, then swept backward.  The noise of the
-// forward sweep is either stored by it (the reparameterisation draws it in advance, eq.
-// reparam_epsilon) and read back, or regenerated from the counter-based stream.  Because the
+// with a checkpoint at every step, one reverse sweep rebuilds each step from the state before it
+// and differentiates it; otherwise segments are processed last to first, each recomputed forward
+// from its checkpoint with the stored ancestors and stored s_t into a segment buffer, then swept
+// backward.  States of a multiple of four components go through the every-step sweep one
+// particle at a time, so that a lane keeps only its particles' adjoints across steps.  The
+// noise of the forward sweep is either stored by it (the reparameterisation draws it in
+// advance, eq. reparam_epsilon) and read back, or regenerated from the counter-based stream.  Because the
 // normalised weights sum to one, the adjoint of the per-step log-weights between two resampling
 // steps is the normalised weight vector at the later one (or at T); it is carried per particle
 // as `wb`.  At a resampling step the state adjoint is scatter-added from offspring to parents.
-// The parameter adjoint is accumulated in FP64 per thread and reduced once per item.
+// The parameter adjoint is accumulated in FP64 per thread (for states of a multiple of four
+// components: per wave, in LDS) and reduced once per item.
 //
 // The series y, the per-step log normalisers s_t and the resampling flags of the current item
 // live in LDS (dynamic shared memory sized by the longest series).
@@ -210,8 +215,9 @@ struct SysTargets {
 };
 
 // Ancestors of this thread's offspring slots under systematic resampling.  The weight prefix of
-// slot j0 + p is base + part_p (the exclusive prefix of the lane plus its running sum).  Each parent marks the first offspring it owns, and an exclusive max-scan over
-// the markers hands every offspring the last parent that started at or before it; a reader
+// slot j0 + p is base + part_p (the exclusive prefix of the lane plus its running sum).  Each
+// parent marks the first offspring it owns, and an exclusive max-scan over the markers hands
+// every offspring the last parent that started at or before it; a reader
 // clears its own markers after use.  FAST: M fills the tile (a power of two), so no slot is
 // padding.  `dummy` is a per-lane marker slot for parents that own nothing.
 template <bool FAST, int WAVES, int PPL, typename R>
