@@ -43,7 +43,8 @@ enum { ORC_SYSTEMATIC = 0, ORC_MULTINOMIAL = 1 };
 
 /* ORC_SIR: the discrete-time SIR model of Sec. IV-B, state x = (S, I) (R = N_pop - S - I),
  * theta = (beta, gamma) on their natural scale:
- *   S_t = S - beta I S / N_pop + s_e e_b,   I_t = I + beta I S / N_pop - gamma I - s_e e_b + s_e e_g,
+ *   S_t = S - beta I S / N_pop + s_e e_b,
+ *   I_t = I + beta I S / N_pop - gamma I - s_e e_b + s_e e_g,
  *   y_t = I_t + s_y w  (one observation per step),   x_0 = (N_pop - I_0, I_0),
  * with the model constants (N_pop, I_0, s_e^2, s_y), default (763, 1, 0.5, 5) (C28-C30). */
 typedef struct {

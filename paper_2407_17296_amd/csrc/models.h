@@ -277,7 +277,8 @@ struct ModelLG1DOpt {
 };
 
 // The discrete-time SIR model of Sec. IV-B: state (S, I), R = N_pop - S - I implied,
-//   S_t = S - beta I S / N_pop + s_e e_0,  I_t = I + beta I S / N_pop - gamma I - s_e e_0 + s_e e_1,
+//   S_t = S - beta I S / N_pop + s_e e_0,
+//   I_t = I + beta I S / N_pop - gamma I - s_e e_0 + s_e e_1,
 //   y = I_t + s_y w,  x_0 = (N_pop - I_0, I_0);  theta = (beta, gamma) on their natural scale.
 // Constants (N_pop, I_0, s_e^2, s_y).  The start is fixed, so init_adj has nothing to add.
 template <typename R>

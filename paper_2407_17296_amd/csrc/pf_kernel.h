@@ -34,10 +34,10 @@
 // backward.  States of a multiple of four components go through the every-step sweep one
 // particle at a time, so that a lane keeps only its particles' adjoints across steps.  The
 // noise of the forward sweep is either stored by it (the reparameterisation draws it in
-// advance, eq. reparam_epsilon) and read back, or regenerated from the counter-based stream.  Because the
-// normalised weights sum to one, the adjoint of the per-step log-weights between two resampling
-// steps is the normalised weight vector at the later one (or at T); it is carried per particle
-// as `wb`.  At a resampling step the state adjoint is scatter-added from offspring to parents.
+// advance, eq. reparam_epsilon) and read back, or regenerated from the counter-based stream.
+// Because the normalised weights sum to one, the adjoint of the per-step log-weights between two
+// resampling steps is the normalised weight vector at the later one (or at T); it is carried
+// per particle as `wb`.  At a resampling step the state adjoint is scatter-added from offspring to parents.
 // The parameter adjoint is accumulated in FP64 per thread (for states of a multiple of four
 // components: per wave, in LDS) and reduced once per item.
 //
