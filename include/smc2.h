@@ -266,7 +266,7 @@ smc2_status smc2_philox_probe(int32_t R, const uint32_t *ctr, const uint32_t *n,
 smc2_status smc2_tile_info(int32_t tile, int32_t d_x, int32_t *max_particles, int32_t *waves,
                            int32_t *per_lane);
 
-/* Library version string. */
+/* Library version string.  0.2: smc2_model carries prior_kind and constants (the SIR model). */
 const char *smc2_version(void);
 
 #ifdef __cplusplus

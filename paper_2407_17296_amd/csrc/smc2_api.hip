@@ -297,7 +297,7 @@ int grid_slots_for(smc2_ctx *ctx, const smc2_model *m, const smc2_pf_opts *o, in
 
 extern "C" {
 
-const char *smc2_version(void) { return "smc2-mi355x 0.1 (gfx950)"; }
+const char *smc2_version(void) { return "smc2-mi355x 0.2 (gfx950)"; }
 
 const char *smc2_last_error(void) { return g_err.c_str(); }
 
