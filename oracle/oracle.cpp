@@ -513,6 +513,9 @@ int run_pf(const orc_model *mdl, const orc_pf_opts *opt, const R *theta, int T, 
       std::vector<double> ds(D, 0.0);
       for (int j = 0; j < M; ++j) {
         double W = e[j] / Sre;
+        /* a particle of exactly zero weight takes no part, even where its state has overflowed
+         * and its own tangent is not finite (C32) */
+        if (W == 0.0) continue;
         for (int p = 0; p < D; ++p) ds[p] += W * lwd[(size_t)j * D + p];
       }
       for (int p = 0; p < D; ++p) lld[p] += ds[p];

@@ -234,3 +234,22 @@ def test_samples_leaving_the_support_get_zero_weight(oracle):
     assert bad[1:].any()  # the large step does leave the support
     assert np.all(lw[bad] == -np.inf)
     assert np.all(np.isfinite(lw[~bad]) | (lw[~bad] == -np.inf))
+
+
+def test_overflowed_particles_take_no_part_in_the_gradient(oracle):
+    """With a vague observation (s_y = 200) nothing is resampled, and particles whose infected
+    count went negative grow without bound until their state overflows; their weight is then
+    exactly zero.  The gradient (such particles taking no part, C32) is finite and equals central
+    differences of the estimate with the random numbers held fixed."""
+    w = synth.make(5)
+    m = _sir(oracle, constants=[NPOP, I0, VAR, 200.0])
+    y = w.y[0, :, 0].reshape(-1, 1)
+    th, h = np.array([0.6809537166263908, 0.23789620003663003]), 1e-7
+    out = oracle.pf(m, th, y, 64, w.seed, 1, 7, want_trace=True)
+    assert out["flags"].sum() == 0 and np.all(np.isfinite(out["grad"]))
+    for p in range(2):
+        e = np.zeros(2)
+        e[p] = h
+        fd = (oracle.pf(m, th + e, y, 64, w.seed, 1, 7)["loglik"] -
+              oracle.pf(m, th - e, y, 64, w.seed, 1, 7)["loglik"]) / (2 * h)
+        assert out["grad"][p] == pytest.approx(fd, rel=1e-6)
