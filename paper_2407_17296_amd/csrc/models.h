@@ -316,8 +316,9 @@ struct ModelSIR : Bootstrap<ModelSIR<R>, R> {
     const R d = gI - gS;
     tb[0] += (Acc)mulz(d, I * S * inp);
     tb[1] -= (Acc)mulz(gI, I);
-    xb[0] = fmar(bn * I, d, gS);
-    xb[1] = fmar(bn * S, d, fmar(-gam, gI, gI));
+    // a zero adjoint adds nothing, also where the state has overflowed (I or S infinite)
+    xb[0] = d == (R)0 ? gS : fmar(bn * I, d, gS);
+    xb[1] = d == (R)0 ? fmar(-gam, gI, gI) : fmar(bn * S, d, fmar(-gam, gI, gI));
   }
   __device__ R logg(const R *y, const R *x) const {
     const R r = (y[0] - x[1]) * isy;
