@@ -205,3 +205,22 @@ def test_outer_step_at_large_and_ragged_population(oracle, N):
     run.close()
     resampled = [k + 1 for k in range(K) if _check_iteration(oracle, w, rec, k, pf_items=4)]
     say("  N=%d: %d iterations match; resampled at %s" % (N, K, resampled))
+
+
+def test_sir_samples_leaving_the_uniform_support(oracle):
+    """With a vaguer observation (s_y = 200, so the population does not collapse onto one
+    sample) and a large Langevin step, the SIR sampler moves some samples outside U(0, 1): their
+    prior is zero, so the reweighting kernel gives them weight zero (eq. l_weights), iteration
+    by iteration as the oracle's functions do on the GPU's own inputs."""
+    w = synth.make(5, N=64, M=64)
+    w.constants = np.array([763.0, 1.0, 0.5, 200.0])
+    w.gamma = 0.1
+    K = 4
+    run, rec = driver.run_smc2(w, K=K, precision=smc2.FP64)
+    run.close()
+    th = rec.theta[:, 0]
+    outside = ((th < 0.0) | (th > 1.0)).any(axis=2)
+    say("  samples outside the support per iteration: %s" % outside.sum(axis=1))
+    assert outside[1:].any()
+    for k in range(K):
+        _check_iteration(oracle, w, rec, k, pf_items=4)
