@@ -48,27 +48,30 @@ PEAK_VALU_TSLOTS = 256 * 128 * 2.4e9 / 1e12  # T FP32 lane-slots per second
 #              parameter adjoint 3, scatter-add to the parent at a resampled step 2 r
 #                                                                                 -> 14 + 2 r
 # Rebuilding the step in the adjoint (from checkpoints) is implementation work, not counted.
-def alg_slots_per_particle_step(M, r):
-    noise, model, normalise = 42.0, 9.0, 13.0
+def alg_slots_per_particle_step(M, r, d=1):
+    """The count above; for a d-component state the noise, the model and its transposed
+    derivatives scale with d (an estimate for the other models, exact in form only for the
+    linear-Gaussian ones)."""
+    noise, model, normalise = 42.0 * d, 9.0 * d, 13.0
     forward = noise + model + normalise + 30.0 * r
-    adjoint = 14.0 + 2.0 * r
+    adjoint = 11.0 * d + 3.0 + 2.0 * r * d
     return forward + adjoint
 
 
-def algorithmic_bytes_per_particle_step(r, c, rs, d=1):
+def algorithmic_bytes_per_particle_step(r, c, rs, d=1, lw_skip=True):
     """HBM bytes the method must move per particle-step: the int32 ancestor written in the
     forward and read in the adjoint at a resampled step (fraction r), and the checkpoint written
     and read once every c steps (rs bytes per value): the state, and the carried log-weight
     unless the step before resampled (then every log-weight is -log M and none is stored)."""
-    return r * 8.0 + 2.0 * (d + 1.0 - r) * rs / c
+    return r * 8.0 + 2.0 * (d + (1.0 - r if lw_skip else 1.0)) * rs / c
 
 
-def design_bytes_per_particle_step(r, c, rs, store_noise, d=1):
+def design_bytes_per_particle_step(r, c, rs, store_noise, d=1, lw_skip=True):
     """HBM bytes the chosen configuration moves by construction: ancestors and checkpoints as
     above, the stored noise (written once, read once), and for c > 1 the segment rows (state
     before the step, the noise when not stored, and the weight at resampled steps) written by
     the recomputation and read by the reverse sweep, plus the ancestors read again there."""
-    b = algorithmic_bytes_per_particle_step(r, c, rs, d)
+    b = algorithmic_bytes_per_particle_step(r, c, rs, d, lw_skip)
     if store_noise:
         b += 2.0 * d * rs * (1.0 if c == 1 else 1.5)
     if c > 1:
@@ -77,9 +80,24 @@ def design_bytes_per_particle_step(r, c, rs, store_noise, d=1):
     return b
 
 
+MODEL_TEXT = {0: "1-D linear-Gaussian SSM", 1: "16-dimensional diagonal linear-Gaussian SSM",
+              2: "nonlinear growth model", 3: "stochastic-volatility series",
+              5: "SIR epidemic model"}
+MODEL_KERNEL = {0: "ModelLG1D<float>", 1: "ModelLGDiag<float, 16>", 2: "ModelGrowth<float>",
+                3: "ModelSV<float>", 5: "ModelSIR<float>"}
+
+
 def _timed_graph(run, steps, warmup):
+    """Seconds of `steps` graph replays, their wall time, and the seconds of the eager first
+    iteration (prior draws, the filter, reweighting: the worst-case resampling rate)."""
     import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
     run.first_iteration()
+    b.record()
+    torch.cuda.synchronize()
+    first_s = a.elapsed_time(b) / 1e3
     run.capture()
     for _ in range(warmup):
         run.replay()
@@ -92,7 +110,7 @@ def _timed_graph(run, steps, warmup):
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return start.elapsed_time(stop) / 1e3, wall
+    return start.elapsed_time(stop) / 1e3, wall, first_s
 
 
 def _kernel_duration(run, launches):
@@ -151,7 +169,18 @@ def cpu_baseline(w, seconds, threads):
     dt = time.perf_counter() - t0
     return dict(value=done / dt, unit="particle-steps/s", cores=threads, kind="oracle",
                 sample="%d filters of M=%d, T=%d (%s) at theta near the data-generating value, "
-                       "%.1f s wall" % (i, w.M, int(w.T_len[0]), w.name, dt))
+                       "%.1f s wall, on %s" % (i, w.M, int(w.T_len[0]), w.name, dt, _cpu_model()))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def measure(w, precision, steps, warmup, with_kernel=True, tune=True, force=None):
@@ -162,10 +191,10 @@ def measure(w, precision, steps, warmup, with_kernel=True, tune=True, force=None
         t = autotune.tune(w, precision) if tune else dict(tile=0, ckpt=0, store_noise=0)
     run = driver.SMC2Run(w, precision=precision, tile=t["tile"], ckpt_interval=t["ckpt"],
                          store_noise=t.get("store_noise", 1))
-    gpu_s, wall = _timed_graph(run, steps, warmup)
+    gpu_s, wall, first_s = _timed_graph(run, steps, warmup)
     out = dict(seconds=gpu_s, wall=wall, ms_per_step=1e3 * gpu_s / steps,
                value=w.particle_steps() * steps / gpu_s, tile=t["tile"], ckpt=t["ckpt"],
-               store_noise=t.get("store_noise", 1))
+               store_noise=t.get("store_noise", 1), first_s=first_s)
     if with_kernel:
         out["kernel_s"] = _kernel_duration(run, max(3, min(10, steps)))
         out["resample_fraction"] = _resample_fraction(run)
@@ -266,14 +295,16 @@ def main():
     c_sqrt = int(np.ceil(np.sqrt(w.T_max)))
     c = mixed["ckpt"] or c_sqrt
     _, waves, ppl = _smc2.smc2_tile_info(mixed["tile"], w.d) if mixed["tile"] else (0, 0, 0)
-    slots = alg_slots_per_particle_step(w.M, r)
+    lw_skip = w.d < 4  # the kernel stores every checkpoint's log-weights for wide states
+    slots = alg_slots_per_particle_step(w.M, r, w.d)
     achieved = slots * ps_launch / mixed["kernel_s"] / 1e12
-    hbm_bytes = algorithmic_bytes_per_particle_step(r, c_sqrt, 4) * ps_launch
-    design_bytes = design_bytes_per_particle_step(r, c, 4, mixed["store_noise"]) * ps_launch
+    hbm_bytes = algorithmic_bytes_per_particle_step(r, c_sqrt, 4, w.d, lw_skip) * ps_launch
+    design_bytes = design_bytes_per_particle_step(r, c, 4, mixed["store_noise"], w.d,
+                                                  lw_skip) * ps_launch
     traffic = recorded_traffic(w.name, mixed["tile"], 1, c, mixed["store_noise"])
     roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TSLOTS, unit="Tslot/s",
                 frac=achieved / PEAK_VALU_TSLOTS, traffic=traffic,
-                kernel="pf_fwd_adj_kernel<float, ModelLG1D<float>, %d, %d>" % (waves, ppl),
+                kernel="pf_fwd_adj_kernel<float, %s, %d, %d>" % (MODEL_KERNEL[w.kind], waves, ppl),
                 tile=mixed["tile"], ckpt_interval=c, store_noise=mixed["store_noise"],
                 kernel_ms=1e3 * mixed["kernel_s"], alg_slots_per_particle_step=slots,
                 resample_fraction=r,
@@ -305,13 +336,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32/f64 mixed",
         "data": "synthetic",
-        "config": {"workload": "%s: 1-D linear-Gaussian SSM, T=%d, N=%d samples, M=%d particles, "
-                               "one SMC2 iteration per step" % (w.name, w.T_max, w.N, w.M),
+        "config": {"workload": "%s: %s, T=%d, N=%d samples, M=%d particles, "
+                               "one SMC2 iteration per step" % (w.name, MODEL_TEXT[w.kind],
+                                                                w.T_max, w.N, w.M),
                    "global_batch": w.N, "seq_len": w.T_max, "particles": w.M,
                    "parallelism": "one GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    line["first_iteration"] = dict(
+        ms=1e3 * mixed["first_s"], value=w.particle_steps() / mixed["first_s"],
+        note="iteration 1, eager: prior draws, the filter and reweighting")
     line.update(res)
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib * 262144, dtype=torch.float32, device="cuda:0")
