@@ -365,3 +365,22 @@ def test_launches_are_reproducible(precision):
     worst = max(rel_err(a[1][s, i], b[1][s, i]) for s in range(w.S) for i in range(w.N))
     say("  relaunch: max relative gradient difference %.1e" % worst)
     assert worst <= tol
+
+
+def test_mixed_form_has_no_loglik_bias_over_many_streams():
+    """The mixed form against the FP64 form on 5120 filters of the full-size 1-D LG workload at
+    the data-generating theta (five iterations' random streams): the mean paired difference of
+    the log-likelihood estimate is zero within 4 standard errors, and the standard error is small
+    enough that a bias of 1e-4 T (0.025 nats) would show."""
+    w = synth.make(1, N=1024, S=1)
+    theta = np.broadcast_to(w.theta_true, (1, w.N, w.D)).copy()
+    ds = []
+    for k in (7, 8, 9, 10, 11):
+        l64, _, _ = gpu_pf(w, theta, precision=smc2.FP64, k=k, want_grad=0)
+        l32, _, _ = gpu_pf(w, theta, precision=smc2.MIXED, k=k, want_grad=0)
+        ds.append((l32 - l64)[0])
+    d = np.concatenate(ds)
+    se = d.std(ddof=1) / np.sqrt(len(d))
+    say("  mixed - FP64 loglik over %d filters: %.4f +- %.4f" % (len(d), d.mean(), se))
+    assert se < 0.025 / 2
+    assert abs(d.mean()) <= 4 * se
