@@ -384,3 +384,18 @@ def test_mixed_form_has_no_loglik_bias_over_many_streams():
     say("  mixed - FP64 loglik over %d filters: %.4f +- %.4f" % (len(d), d.mean(), se))
     assert se < 0.025 / 2
     assert abs(d.mean()) <= 4 * se
+
+
+@pytest.mark.parametrize("precision", [smc2.FP64, smc2.MIXED])
+def test_wide_state_persistent_equals_grid(precision):
+    """The 16-dimensional state in the persistent grid (workgroups pulling several items in turn,
+    the per-wave parameter-adjoint rows in LDS reused) against one workgroup per item."""
+    w = synth.make(2, N=40, M=256, T=30)
+    theta = spread_theta(w, 0.05, seed=52)
+    a = gpu_pf(w, theta, precision=precision, k=2, persistent=0, ckpt=1)
+    b = gpu_pf(w, theta, precision=precision, k=2, persistent=1, ckpt=1)
+    assert np.array_equal(a[0], b[0])
+    tol = 1e-12 if precision == smc2.FP64 else 1e-5
+    worst = max(rel_err(a[1][0, i], b[1][0, i]) for i in range(w.N))
+    say("  d = 16 persistent vs grid: max relative gradient difference %.1e" % worst)
+    assert worst <= tol
