@@ -399,3 +399,30 @@ def test_wide_state_persistent_equals_grid(precision):
     worst = max(rel_err(a[1][0, i], b[1][0, i]) for i in range(w.N))
     say("  d = 16 persistent vs grid: max relative gradient difference %.1e" % worst)
     assert worst <= tol
+
+
+@pytest.mark.parametrize("tile,store_noise", [(9, 1), (9, 0), (10, 1)])
+def test_full_size_in_the_benchmarked_configuration(oracle, tile, store_noise):
+    """The launch configurations the benchmark's tuner picks on the full-size 1-D LG workload
+    (a checkpoint at every step, noise stored or regenerated): the FP64 form against the oracle
+    on sampled items, and the mixed form against the FP64 form statistically."""
+    w = synth.make(1)
+    theta = spread_theta(w, 0.3, seed=53)
+    sample = [(0, i) for i in (3, 400, 1000)]
+    ll, g, tr = gpu_pf(w, theta, tile=tile, ckpt=1, store_noise=store_noise, k=6,
+                       trace_items=sample)
+    _check_fp64(oracle, w, theta, ll, g, tr, k=6, items=sample, min_gated=0.3)
+    wt = synth.make(1, N=1024)
+    at = np.broadcast_to(wt.theta_true, (1, wt.N, wt.D)).copy()
+    l64, g64, _ = gpu_pf(wt, at, precision=smc2.FP64, tile=tile, ckpt=1,
+                         store_noise=store_noise, k=12)
+    l32, g32, _ = gpu_pf(wt, at, precision=smc2.MIXED, tile=tile, ckpt=1,
+                         store_noise=store_noise, k=12)
+    d = (l32 - l64)[0]
+    se = d.std(ddof=1) / np.sqrt(len(d))
+    dg = (g32 - g64)[0]
+    seg = dg.std(axis=0, ddof=1) / np.sqrt(len(d))
+    say("  tile %d store_noise %d: mixed - FP64 loglik %.3f +- %.3f" % (tile, store_noise,
+                                                                      d.mean(), se))
+    assert abs(d.mean()) <= 4 * se + 1e-9
+    assert np.all(np.abs(dg.mean(axis=0)) <= 4 * seg + 1e-9)
