@@ -426,3 +426,15 @@ def test_full_size_in_the_benchmarked_configuration(oracle, tile, store_noise):
                                                                       d.mean(), se))
     assert abs(d.mean()) <= 4 * se + 1e-9
     assert np.all(np.abs(dg.mean(axis=0)) <= 4 * seg + 1e-9)
+
+
+@pytest.mark.parametrize("index,M,T", [(0, 4096, 30), (0, 4000, 30), (3, 4096, 20),
+                                       (2, 2048, 10), (5, 2048, 20)])
+def test_fp64_largest_particle_counts(oracle, index, M, T):
+    """The largest filters the library builds (4096 particles for scalar states, 2048 for the
+    two- and 16-component ones), full and ragged, every item with its ancestry."""
+    w = synth.make(index, N=3, M=M, T=T)
+    theta = spread_theta(w, 0.05, seed=54 + M)
+    items = [(0, i) for i in range(w.N)]
+    ll, g, tr = gpu_pf(w, theta, k=2, trace_items=items)
+    _check_fp64(oracle, w, theta, ll, g, tr, k=2)
