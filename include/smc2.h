@@ -172,7 +172,7 @@ smc2_status smc2_ctx_device_status(smc2_ctx *ctx, void *stream);
  *   grad     dev  [S][N][D] FP64 out (NULL iff opts->want_grad == 0).
  * Errors: SMC2_E_INVALID_ARG for NULL pointers, sizes < 1 (T_len >= 0), sizes beyond the
  * reservation or T_len[s] > T_max; SMC2_E_UNSUPPORTED for M above the largest built tile
- * (4096 for d=1, 2048 for d=16) or an unknown model/precision. */
+ * (4096 for d_x = 1, 2048 for d_x = 2 and 16) or an unknown model/precision. */
 smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const smc2_pf_opts *opts,
                                 int32_t S, int32_t N, int32_t M, const int32_t *T_len,
                                 int32_t T_max, const double *theta, const double *y,
@@ -203,7 +203,8 @@ typedef struct {
 /* Reweight, normalise, ESS and resample, one workgroup per series.
  *   On entry cur->theta holds theta_k, cur->loglik the filter's estimate and cur->grad_logpost
  *   the filter's gradient of the log-likelihood.  The call first adds the prior:
- *   logpost = log p(theta) + loglik, grad_logpost += grad log p(theta).  Then the weight:
+ *   logpost = log p(theta) + loglik, grad_logpost += grad log p(theta) (logpost = -inf, so a
+ *   weight of zero, outside a uniform prior's support).  Then the weight:
  *     first_iteration = 1: log w = loglik (eq. init_weights with q_1 = prior);
  *     otherwise          : log w = prev->logw + logpost - prev->logpost
  *                          + log N(-p_k; 0, G) - log N(p_{k-1}; 0, G),
