@@ -161,7 +161,8 @@ smc2_status smc2_ctx_device_status(smc2_ctx *ctx, void *stream);
  * particle gradients inherited from the parent).  The gradient is computed in reverse mode: a
  * forward sweep that stores int32 ancestors at resampling steps and (x, log W) checkpoints
  * every ckpt_interval steps, then a backward sweep that recomputes each segment from its
- * checkpoint with the stored ancestors (and the stored noise with store_noise = 1).
+ * checkpoint with the stored ancestors (and the stored noise with store_noise = 1); with
+ * ckpt_interval = 1 nothing is recomputed: each step is rebuilt from the state before it.
  *
  *   T_len    host [S]: length of series s (0 <= T_len[s] <= T_max); y rows past it are ignored.
  *   theta    dev  [S][N][D] FP64.
