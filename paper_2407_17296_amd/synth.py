@@ -121,7 +121,7 @@ def _simulate(kind, theta, T, d, rng):
 
 
 def make(index, N=None, M=None, K=None, S=None, T=None):
-    """Build workload `index` (0..4).  N, M, K, S, T override the sizes (T caps every T_s)."""
+    """Build workload `index` (0..5).  N, M, K, S, T override the sizes (T caps every T_s)."""
     i = int(index)
     data_seed, seed = 20240724 + i, 17296 + i
     rng = np.random.default_rng(data_seed)
