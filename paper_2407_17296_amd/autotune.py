@@ -83,7 +83,9 @@ def time_config(w, precision, tile, ckpt, store_noise=1, reps=3, seed_theta=0):
 def tune(w, precision, reps=3, use_cache=True, verbose=False):
     """Best (tile, ckpt, store_noise) for workload w at `precision`; returns a dict with the
     timings."""
-    name = torch.cuda.get_device_name(0)
+    # the architecture name: the marketing name can read as empty (e.g. under a profiler)
+    props = torch.cuda.get_device_properties(0)
+    name = getattr(props, "gcnArchName", "") or torch.cuda.get_device_name(0)
     k = key(w, precision, name)
     cache = {}
     if use_cache and os.path.exists(CACHE):
