@@ -54,8 +54,9 @@ typedef enum {
 /* State-space models (paper eqs. xt and yt).  Parameters are unconstrained:
  *   SMC2_MODEL_LG1D    d=1,  D=3:  theta = (a, log sx, log sy);
  *                      x_t = a x_{t-1} + sx v, y_t = x_t + sy w, x_0 ~ N(0, 1)
- *   SMC2_MODEL_LG_DIAG d>=1, D=d+2: theta = (A_11..A_dd, log sx, log sy);
+ *   SMC2_MODEL_LG_DIAG d=16, D=18: theta = (A_11..A_dd, log sx, log sy);
  *                      x_t = A x_{t-1} + sx v with A diagonal, y_t = x_t + sy w, x_0 ~ N(0, I)
+ *                      (the kernels are built for d = 16 only)
  *   SMC2_MODEL_GROWTH  d=1,  D=2:  theta = (log sx, log sy);
  *                      x_t = x/2 + 25 x/(1+x^2) + 8 cos(1.2 t) + sx v, y_t = x_t^2/20 + sy w,
  *                      x_0 ~ N(0, 1)
