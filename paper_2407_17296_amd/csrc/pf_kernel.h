@@ -366,6 +366,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
     // a checkpoint then stores the state only, and the adjoint takes the constant (not for wide
     // states, whose checkpoints are mostly state and whose registers are scarce)
     bool lw_uniform = !kWide;
+    // the systematic resampling words of 64 consecutive steps, one per lane (drawn by the
+    // vector unit once per 64 steps instead of by the scalar unit at every resampling step)
+    uint32_t nu_word = 0;
+    int nu_base = -1;
     for (int t = 1; t <= T; ++t) {
       if (ck_left == 0) {
         R *cks = ck + (size_t)ck_idx * (DX + 1) * LD;
@@ -468,7 +472,13 @@ void pf_fwd_adj_kernel(PFArgs A) {
       int a[PPL];
       if (systematic) {
         SysTargets tg;
-        tg.nu = ((double)philox4x32_10(kNoSlot, (uint32_t)t, fid, c3r, seed).x + 1.0) * 0x1p-32;
+        const int tb = (t - 1) & ~63;
+        if (tb != nu_base) {
+          nu_base = tb;
+          nu_word = philox4x32_10(kNoSlot, (uint32_t)(tb + 1 + lane), fid, c3r, seed).x;
+        }
+        const uint32_t wnu = (uint32_t)__builtin_amdgcn_readlane((int)nu_word, (t - 1) & 63);
+        tg.nu = ((double)wnu + 1.0) * 0x1p-32;
         tg.M = M;
         tg.Md = Md;
         tg.inv_Md = 1.0 / Md;
