@@ -53,6 +53,42 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
   return make_uint4(c0, c1, c2, c3);
 }
 
+// NB Philox4x32-10 blocks that differ only in the first counter word, run under one key
+// schedule (the same numbers as NB calls of philox4x32_10, with the scalar key advance shared).
+template <int NB>
+__device__ __forceinline__ void philox4x32_10_n(const uint32_t (&c0)[NB], uint32_t c1,
+                                                uint32_t c2, uint32_t c3, uint64_t seed,
+                                                uint4 (&out)[NB]) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  asm volatile("" : "+s"(k0), "+s"(k1));  // as in philox4x32_10
+  uint32_t a[NB], b[NB], c[NB], d[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    a[i] = c0[i];
+    b[i] = c1;
+    c[i] = c2;
+    d[i] = c3;
+  }
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)a[i];
+      const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[i];
+      const uint32_t n0 = (uint32_t)(p1 >> 32) ^ b[i] ^ k0;
+      const uint32_t n2 = (uint32_t)(p0 >> 32) ^ d[i] ^ k1;
+      b[i] = (uint32_t)p1;
+      d[i] = (uint32_t)p0;
+      a[i] = n0;
+      c[i] = n2;
+    }
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) out[i] = make_uint4(a[i], b[i], c[i], d[i]);
+}
+
 // Box-Muller (Box & Muller 1958) on one word pair: u1 = (wa + 1) 2^-32 in (0, 1],
 // u2 = wb 2^-32 in [0, 1); z0 = r cos(2 pi u2), z1 = r sin(2 pi u2), r = sqrt(-2 ln u1).
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &z0, double &z1) {

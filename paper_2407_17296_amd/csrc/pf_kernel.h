@@ -95,13 +95,17 @@ __device__ __forceinline__ R pick4(const R (&z)[4], int i) {
 template <typename R, int DX, int PPL>
 __device__ __forceinline__ void filter_noise(int j0, uint32_t fid, uint32_t c3, uint32_t t,
                                              uint64_t seed, R (&e)[PPL][DX]) {
-  if constexpr (DX == 1 && PPL % 4 == 0) {
+  if constexpr (DX == 1 && PPL % 4 == 0 && PPL > 4) {  // several blocks, one key schedule
+    constexpr int NB = PPL / 4;
+    uint32_t c0[NB];
+    uint4 w[NB];
 #pragma unroll
-    for (int b = 0; b < PPL / 4; ++b) {
-      R z[4];
-      normals4<R>((uint32_t)(j0 >> 2) + b, t, fid, c3, seed, z);
+    for (int b = 0; b < NB; ++b) c0[b] = (uint32_t)(j0 >> 2) + b;
+    philox4x32_10_n<NB>(c0, t, fid, c3, seed, w);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) e[4 * b + r][0] = z[r];
+    for (int b = 0; b < NB; ++b) {
+      box_muller(w[b].x, w[b].y, e[4 * b][0], e[4 * b + 1][0]);
+      box_muller(w[b].z, w[b].w, e[4 * b + 2][0], e[4 * b + 3][0]);
     }
   } else if constexpr (DX % 4 == 0) {
 #pragma unroll
@@ -113,16 +117,30 @@ __device__ __forceinline__ void filter_noise(int j0, uint32_t fid, uint32_t c3, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) e[p][4 * b + r] = z[r];
       }
-  } else if constexpr (DX == 2 && PPL % 2 == 0) {
+  } else if constexpr (DX == 1 && PPL == 4) {
+    R z[4];
+    normals4<R>((uint32_t)(j0 >> 2), t, fid, c3, seed, z);
 #pragma unroll
-    for (int b = 0; b < PPL / 2; ++b) {  // slots j0 + 2b and j0 + 2b + 1 share a block
-      R z[4];
-      normals4<R>((uint32_t)(j0 >> 1) + b, t, fid, c3, seed, z);
-      e[2 * b][0] = z[0];
-      e[2 * b][1] = z[1];
-      e[2 * b + 1][0] = z[2];
-      e[2 * b + 1][1] = z[3];
+    for (int r = 0; r < 4; ++r) e[r][0] = z[r];
+  } else if constexpr (DX == 2 && PPL % 2 == 0 && PPL > 2) {
+    constexpr int NB = PPL / 2;  // slots j0 + 2b and j0 + 2b + 1 share block b
+    uint32_t c0[NB];
+    uint4 w[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) c0[b] = (uint32_t)(j0 >> 1) + b;
+    philox4x32_10_n<NB>(c0, t, fid, c3, seed, w);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      box_muller(w[b].x, w[b].y, e[2 * b][0], e[2 * b][1]);
+      box_muller(w[b].z, w[b].w, e[2 * b + 1][0], e[2 * b + 1][1]);
     }
+  } else if constexpr (DX == 2 && PPL == 2) {
+    R z[4];
+    normals4<R>((uint32_t)(j0 >> 1), t, fid, c3, seed, z);
+    e[0][0] = z[0];
+    e[0][1] = z[1];
+    e[1][0] = z[2];
+    e[1][1] = z[3];
   } else if constexpr (DX == 2) {
     static_assert(PPL == 1, "two-component states take one or an even number of slots per lane");
     R z[4];
