@@ -237,7 +237,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=1,
+                    help="workload index (synth.make): 0 small 1-D LG, 1 1-D LG T=250 N=1024 "
+                         "M=1024, 2 16-dim LG, 3 growth, 4 SV, 5 SIR")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-growth", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -254,14 +256,14 @@ def main():
     ap.add_argument("--store-noise", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the hot path shards by parameter sample and this build "
-              "measures one GPU's share; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU (the hot path shards by parameter sample, and one GPU's "
+              "share is what it times); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2407_17296_amd import smc2, synth
     torch.cuda.init()
-    w = synth.make(args.config)
+    w = synth.make(args.workload)
     print("[bench] workload %s S=%d N=%d M=%d T=%d, %d warmup + %d timed iterations" % (
         w.name, w.S, w.N, w.M, w.T_max, args.warmup, args.steps), file=sys.stderr, flush=True)
     tune = not args.no_tune

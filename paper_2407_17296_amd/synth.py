@@ -172,9 +172,11 @@ def make(index, N=None, M=None, K=None, S=None, T=None):
         extra = dict(prior_mu=np.zeros(D), prior_sd=np.ones(D), dy=1,
                      prior_kind=np.full(D, PRIOR_KIND_UNIFORM, dtype=np.int32),
                      constants=np.array(SIR_CONSTANTS))
-    name = f"config{i}_{MODEL_NAMES[kind]}" if i < 5 else "sir_outbreak_synthetic"
-    return Workload(index=i, name=name, kind=kind, d=d, D=D, S=Ss, N=int(N or Nn),
-                    M=int(M or Mm), K=int(K or Kk), gamma=float(gam), T_len=T_len, y=y,
+    n_, m_ = int(N or Nn), int(M or Mm)
+    name = ("sir_outbreak" if kind == SIR else MODEL_NAMES[kind]) + \
+        (f"_S{Ss}" if Ss > 1 else "") + f"_T{T_max}_N{n_}_M{m_}"
+    return Workload(index=i, name=name, kind=kind, d=d, D=D, S=Ss, N=n_,
+                    M=m_, K=int(K or Kk), gamma=float(gam), T_len=T_len, y=y,
                     theta_true=th, seed=seed, data_seed=data_seed,
                     **({"prior_mu": np.zeros(D), "prior_sd": np.ones(D)} | extra))
 
