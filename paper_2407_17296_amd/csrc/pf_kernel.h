@@ -230,6 +230,14 @@ struct SysTargets {
     }
     return lo;
   }
+  // The estimate alone: floor(z) + 1, and whether z lies within kTieMargin of an integer (then
+  // upto must decide).
+  __device__ int estimate(double P, bool &near) const {
+    const double z = P * inv_tot * Md - nu, fz = floor(z), fr = z - fz;
+    const int g = (int)fmin(fmax(fz + 1.0, 0.0), Md);
+    near = near || !(fr > kTieMargin && fr < 1.0 - kTieMargin);
+    return P < tot ? g : M;
+  }
 };
 
 // Ancestors of this thread's offspring slots under systematic resampling.  The weight prefix of
@@ -245,16 +253,31 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
                                                      int dummy) {
   const double tot = tg.tot;
   int prev = tg.upto<FAST>(fmin(base, tot));
+  // the lane's counts from the estimate; if any of them lies near a tie, all are redone exactly
+  int cm[PPL];
+  bool near = false;
   double part = 0.0;
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
-    const int m = j0 + p;
     part += (double)ew[p];
-    const double P = (m == M - 1) ? tot : fmin(base + part, tot);
-    int cm = tg.upto<FAST>(P);
-    if (!FAST && m >= M) cm = prev;
-    atomicMax(&sh_mark[cm > prev ? prev : dummy], m);
-    prev = max(prev, cm);
+    const double P = (j0 + p == M - 1) ? tot : fmin(base + part, tot);
+    cm[p] = tg.estimate(P, near);
+  }
+  if (near) {
+    part = 0.0;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      part += (double)ew[p];
+      const double P = (j0 + p == M - 1) ? tot : fmin(base + part, tot);
+      cm[p] = tg.upto<FAST>(P);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const int m = j0 + p;
+    if (!FAST && m >= M) cm[p] = prev;
+    atomicMax(&sh_mark[cm[p] > prev ? prev : dummy], m);
+    prev = max(prev, cm[p]);
   }
   __syncthreads();
   int run = -1;
@@ -271,7 +294,9 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
 
 template <typename R, class Model, int WAVES, int PPL>
 __global__ __launch_bounds__(WAVES * 64,
-                             (sizeof(R) == 4 && Model::DX == 1 && PPL <= 4 && WAVES <= 4) ? 4 : 1)
+                             (sizeof(R) == 4 && Model::DX == 1 && PPL <= 4 && WAVES <= 4) ? 4
+                             : (sizeof(R) == 4 && Model::DX == 1 && PPL == 8)            ? 2
+                                                                                         : 1)
 void pf_fwd_adj_kernel(PFArgs A) {
   constexpr int NT = WAVES * 64, MP = NT * PPL, DX = Model::DX, DY = Model::DY, NP = Model::NP;
   constexpr double kNegInf = -__builtin_huge_val();
