@@ -156,6 +156,19 @@ def test_fp64_persistent_equals_grid(ckpt):
     assert np.allclose(a[1], b[1], rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("ckpt", [0, 1])
+def test_fp64_persistent_many_items_per_workgroup(ckpt):
+    """16384 filters of 64 particles over T = 150 steps: far more items than the persistent grid
+    holds, so each workgroup runs several filters in turn, each past the 64-step blocks of its
+    resampling words; estimates bit-identical to one workgroup per item."""
+    w = synth.make(1, N=16384, M=64, T=150)
+    theta = spread_theta(w, 0.05, seed=9)
+    a = gpu_pf(w, theta, k=2, persistent=0, ckpt=ckpt)
+    b = gpu_pf(w, theta, k=2, persistent=1, ckpt=ckpt)
+    assert np.array_equal(a[0], b[0])
+    assert np.allclose(a[1], b[1], rtol=1e-12, atol=1e-12)
+
+
 def test_fp64_checkpoint_intervals_agree(oracle):
     """Every checkpoint interval (every step, a few steps, the square root of T) yields the
     same estimate and the same gradient up to the scatter's summation order."""
