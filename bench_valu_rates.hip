@@ -62,37 +62,49 @@ __global__ void k_fma64(double *out, double seed) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = r;
 }
 
+#define CHECK(expr)                                                                  \
+  do {                                                                               \
+    const hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                          \
+      fprintf(stderr, "%s: %s\n", #expr, hipGetErrorString(e_));                     \
+      return 1;                                                                      \
+    }                                                                                \
+  } while (0)
+
 int main() {
   int dev = 0;
   hipDeviceProp_t prop;
-  hipGetDeviceProperties(&prop, dev);
+  CHECK(hipGetDeviceProperties(&prop, dev));
   const int cus = prop.multiProcessorCount;
   const int threads = 256, blocks = cus * 16;  // 16 waves per SIMD worth of work
   const size_t n = (size_t)threads * blocks;
   void *buf;
-  if (hipMalloc(&buf, n * 8) != hipSuccess) return 1;
+  CHECK(hipMalloc(&buf, n * 8));
   hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
+  CHECK(hipEventCreate(&a));
+  CHECK(hipEventCreate(&b));
   const double clk = prop.clockRate * 1e3;  // Hz
-  auto run = [&](const char *name, auto launch, int instr_per_iter) {
+  auto run = [&](const char *name, auto launch, int instr_per_iter) -> int {
     launch();
-    hipDeviceSynchronize();
-    hipEventRecord(a);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(a));
     launch();
-    hipEventRecord(b);
-    hipEventSynchronize(b);
+    CHECK(hipEventRecord(b));
+    CHECK(hipEventSynchronize(b));
     float ms = 0;
-    hipEventElapsedTime(&ms, a, b);
+    CHECK(hipEventElapsedTime(&ms, a, b));
     const double wave_instr = (double)n / 64 * ITERS * CH * instr_per_iter;
     const double per_cu_cycle = wave_instr / (ms * 1e-3 * clk) / cus;
     printf("%-8s %.3f ms  %.3f wave-instr per CU-cycle (clock %.0f MHz)\n", name, ms, per_cu_cycle,
            clk / 1e6);
+    return 0;
   };
-  run("mad64", [&] { hipLaunchKernelGGL(k_mad64, dim3(blocks), dim3(threads), 0, 0, (uint32_t *)buf, 1u); }, 1);
-  run("fma32", [&] { hipLaunchKernelGGL(k_fma, dim3(blocks), dim3(threads), 0, 0, (float *)buf, 1.0f); }, 1);
-  run("log32", [&] { hipLaunchKernelGGL(k_log, dim3(blocks), dim3(threads), 0, 0, (float *)buf, 1.0f); }, 1);
-  run("fma64", [&] { hipLaunchKernelGGL(k_fma64, dim3(blocks), dim3(threads), 0, 0, (double *)buf, 1.0); }, 1);
-  hipFree(buf);
-  return 0;
+  int rc = 0;
+  rc |= run("mad64", [&] { hipLaunchKernelGGL(k_mad64, dim3(blocks), dim3(threads), 0, 0, (uint32_t *)buf, 1u); }, 1);
+  rc |= run("fma32", [&] { hipLaunchKernelGGL(k_fma, dim3(blocks), dim3(threads), 0, 0, (float *)buf, 1.0f); }, 1);
+  rc |= run("log32", [&] { hipLaunchKernelGGL(k_log, dim3(blocks), dim3(threads), 0, 0, (float *)buf, 1.0f); }, 1);
+  rc |= run("fma64", [&] { hipLaunchKernelGGL(k_fma64, dim3(blocks), dim3(threads), 0, 0, (double *)buf, 1.0); }, 1);
+  CHECK(hipFree(buf));
+  return rc;
 }
