@@ -106,6 +106,23 @@ def test_fp64_lg_diag16_every_step_checkpoints(oracle, M, store_noise):
     _check_fp64(oracle, w, theta, ll, g, tr, k=2)
 
 
+@pytest.mark.parametrize("index,kw,tile,ckpt,store_noise", [
+    (3, dict(N=4, M=512, T=100), 5, 1, 1),      # growth: one wave x 8 per lane, every step
+    (4, dict(S=2, N=3, M=256), 3, 32, 0),       # SV: full series, a checkpoint every 32 steps
+    (5, dict(N=4), 4, 1, 1),                    # SIR: four waves x 1 per lane
+])
+def test_fp64_other_workloads_in_their_benchmarked_configuration(oracle, index, kw, tile, ckpt,
+                                                                  store_noise):
+    """The launch shape, checkpoint interval and noise mode the autotuner picks for the growth,
+    SV and SIR workloads, at their full series lengths, every item with its ancestry."""
+    w = synth.make(index, **kw)
+    theta = spread_theta(w, 0.05, seed=70 + index)
+    items = [(s, i) for s in range(w.S) for i in range(w.N)]
+    ll, g, tr = gpu_pf(w, theta, tile=tile, ckpt=ckpt, k=2, store_noise=store_noise,
+                       trace_items=items)
+    _check_fp64(oracle, w, theta, ll, g, tr, k=2, items=items)
+
+
 def test_fp64_edge_cases(oracle):
     """M = 1 (never resamples), a NaN parameter and parameters no particle can explain."""
     w = synth.make(0, N=4, M=1)
