@@ -102,8 +102,10 @@ def _check(status, where):
         raise SMC2Error(status, where, lib().smc2_last_error().decode())
 
 
-def _ptr(t, dtype=None, name="tensor"):
-    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+def _ptr(t, dtype=None, name="tensor", numel=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL) that holds at least `numel`
+    elements (the kernels index it by the sizes passed alongside, so a smaller buffer is refused
+    here rather than read or written past its end)."""
     if t is None:
         return None
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -112,6 +114,8 @@ def _ptr(t, dtype=None, name="tensor"):
         raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s holds %d elements; the sizes need %d" % (name, t.numel(), numel))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -191,48 +195,77 @@ def smc2_ctx_device_status(ctx, stream=None):
 def smc2_pf_loglik_grad(ctx, model, opts, S, N, M, T_len, T_max, theta, y, seed, iteration,
                         loglik, grad, stream=None):
     T_len = np.ascontiguousarray(T_len, dtype=np.int32)
+    if T_len.size < int(S):
+        raise ValueError("T_len holds %d lengths; S = %d" % (T_len.size, int(S)))
+    SN, D = int(S) * int(N), int(model.c.D)
     _check(lib().smc2_pf_loglik_grad(
         ctx, ctypes.byref(model.c), ctypes.byref(opts), int(S), int(N), int(M),
         T_len.ctypes.data_as(ctypes.c_void_p), int(T_max),
-        _ptr(theta, torch.float64, "theta"), _ptr(y, torch.float64, "y"), int(seed),
-        _ptr(iteration, torch.int32, "iteration"), _ptr(loglik, torch.float64, "loglik"),
-        _ptr(grad, torch.float64, "grad"), _stream(stream)), "smc2_pf_loglik_grad")
+        _ptr(theta, torch.float64, "theta", SN * D),
+        _ptr(y, torch.float64, "y", int(S) * int(T_max) * int(model.c.d_y)), int(seed),
+        _ptr(iteration, torch.int32, "iteration", 1), _ptr(loglik, torch.float64, "loglik", SN),
+        _ptr(grad, torch.float64, "grad", SN * D), _stream(stream)), "smc2_pf_loglik_grad")
 
 
 def smc2_langevin_move(ctx, model, S, N, gamma, random_walk, theta, grad_logpost, seed,
                        iteration, theta_new, p_prev, stream=None):
+    n = int(S) * int(N) * int(model.c.D)
     _check(lib().smc2_langevin_move(
         ctx, ctypes.byref(model.c), int(S), int(N), float(gamma), int(random_walk),
-        _ptr(theta, torch.float64, "theta"), _ptr(grad_logpost, torch.float64, "grad_logpost"),
-        int(seed), _ptr(iteration, torch.int32, "iteration"),
-        _ptr(theta_new, torch.float64, "theta_new"), _ptr(p_prev, torch.float64, "p_prev"),
+        _ptr(theta, torch.float64, "theta", n),
+        _ptr(grad_logpost, torch.float64, "grad_logpost", n),
+        int(seed), _ptr(iteration, torch.int32, "iteration", 1),
+        _ptr(theta_new, torch.float64, "theta_new", n), _ptr(p_prev, torch.float64, "p_prev", n),
         _stream(stream)), "smc2_langevin_move")
 
 
 def population(theta, logpost, grad_logpost, loglik, logw):
-    """A smc2_population over five float64 CUDA tensors."""
-    return smc2_population(*[_ptr(t, torch.float64, n) for t, n in
-                             ((theta, "theta"), (logpost, "logpost"),
-                              (grad_logpost, "grad_logpost"), (loglik, "loglik"), (logw, "logw"))])
+    """A smc2_population over five float64 CUDA tensors (their sizes are kept with it and checked
+    against S, N and D where it is used)."""
+    pop = smc2_population(*[_ptr(t, torch.float64, n) for t, n in
+                            ((theta, "theta"), (logpost, "logpost"),
+                             (grad_logpost, "grad_logpost"), (loglik, "loglik"), (logw, "logw"))])
+    pop.numels = dict(theta=theta.numel(), logpost=logpost.numel(),
+                      grad_logpost=grad_logpost.numel(), loglik=loglik.numel(),
+                      logw=logw.numel())
+    return pop
+
+
+def _check_population(pop, SN, D, name):
+    need = dict(theta=SN * D, logpost=SN, grad_logpost=SN * D, loglik=SN, logw=SN)
+    have = getattr(pop, "numels", None)
+    if have is None:
+        return
+    for k, v in need.items():
+        if have[k] < v:
+            raise ValueError("%s.%s holds %d elements; the sizes need %d" % (name, k, have[k], v))
 
 
 def smc2_reweight_resample(ctx, model, S, N, gamma, random_walk, cur, prev, p_prev,
                            first_iteration, seed, iteration, advance_iteration=0,
                            ancestors=None, ess=None, resampled=None, estimate=None,
                            recycle=None, stream=None):
+    SN, D = int(S) * int(N), int(model.c.D)
+    _check_population(cur, SN, D, "cur")
+    if prev is not None and not first_iteration:
+        _check_population(prev, SN, D, "prev")
     _check(lib().smc2_reweight_resample(
         ctx, ctypes.byref(model.c), int(S), int(N), float(gamma), int(random_walk),
         ctypes.byref(cur), None if prev is None else ctypes.byref(prev),
-        _ptr(p_prev, torch.float64, "p_prev"), int(first_iteration), int(seed),
-        _ptr(iteration, torch.int32, "iteration"), int(advance_iteration),
-        _ptr(ancestors, torch.int32, "ancestors"), _ptr(ess, torch.float64, "ess"),
-        _ptr(resampled, torch.int32, "resampled"), _ptr(estimate, torch.float64, "estimate"),
-        _ptr(recycle, torch.float64, "recycle"), _stream(stream)), "smc2_reweight_resample")
+        _ptr(p_prev, torch.float64, "p_prev", None if first_iteration else SN * D),
+        int(first_iteration), int(seed),
+        _ptr(iteration, torch.int32, "iteration", 1), int(advance_iteration),
+        _ptr(ancestors, torch.int32, "ancestors", SN), _ptr(ess, torch.float64, "ess", int(S)),
+        _ptr(resampled, torch.int32, "resampled", int(S)),
+        _ptr(estimate, torch.float64, "estimate", int(S) * 2 * D),
+        _ptr(recycle, torch.float64, "recycle", int(S) * (1 + 2 * D)), _stream(stream)),
+        "smc2_reweight_resample")
 
 
 def smc2_prior_init(ctx, model, S, N, seed, theta, stream=None):
     _check(lib().smc2_prior_init(ctx, ctypes.byref(model.c), int(S), int(N), int(seed),
-                                 _ptr(theta, torch.float64, "theta"), _stream(stream)),
+                                 _ptr(theta, torch.float64, "theta",
+                                      int(S) * int(N) * int(model.c.D)), _stream(stream)),
            "smc2_prior_init")
 
 
@@ -254,8 +287,8 @@ def smc2_philox_probe(ctr, n, seed, stream=None):
     uniforms = torch.zeros(R, dtype=torch.float64, device=dev)
     n32 = torch.zeros(R, dtype=torch.float32, device=dev)
     u32 = torch.zeros(R, dtype=torch.float32, device=dev)
-    _check(lib().smc2_philox_probe(int(R), _ptr(ctr, torch.int32, "ctr"),
-                                   _ptr(n, torch.int32, "n"), int(seed), _ptr(out), _ptr(normals),
+    _check(lib().smc2_philox_probe(int(R), _ptr(ctr, torch.int32, "ctr", 4 * R),
+                                   _ptr(n, torch.int32, "n", R), int(seed), _ptr(out), _ptr(normals),
                                    _ptr(uniforms), _ptr(n32), _ptr(u32), _stream(stream)),
            "smc2_philox_probe")
     return out, normals, uniforms, n32, u32

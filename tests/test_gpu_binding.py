@@ -1,0 +1,40 @@
+"""Host-side checks of the Python binding over the C ABI."""
+import pytest
+
+from paper_2407_17296_amd import smc2
+
+pytestmark = pytest.mark.gpu
+
+
+def test_binding_refuses_buffers_smaller_than_the_sizes():
+    """The binding checks every device buffer against the sizes passed with it before it calls
+    the library, so a short buffer is an error on the host, not an access past its end."""
+    import torch
+    from paper_2407_17296_amd import synth
+    w = synth.make(0, N=4)
+    model = smc2.Model.from_workload(w)
+    ctx = smc2.Context(model, smc2.pf_opts(), w.S, w.N, w.M, w.T_len, w.T_max)
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    theta = torch.zeros((w.S, w.N, w.D), **f64)
+    y = torch.tensor(w.y, **f64)
+    it = torch.ones(1, dtype=torch.int32, device=dev)
+    ll = torch.zeros((w.S, w.N), **f64)
+    g = torch.zeros((w.S, w.N, w.D), **f64)
+    short = dict(theta=theta[:, :2].contiguous(), y=y[:, :5].contiguous(), loglik=ll[:, :1].contiguous(),
+                 grad=g[:, :3].contiguous())
+    for name, bad in short.items():
+        args = dict(theta=theta, y=y, loglik=ll, grad=g)
+        args[name] = bad
+        with pytest.raises(ValueError, match=name):
+            ctx.pf(args["theta"], args["y"], w.seed, it, args["loglik"], args["grad"])
+    with pytest.raises(ValueError, match="theta_new"):
+        smc2.smc2_langevin_move(ctx.h, model, w.S, w.N, 0.1, 0, theta, g, w.seed, it,
+                                theta[:, :1].contiguous(), torch.zeros_like(theta))
+    with pytest.raises(ValueError, match="theta"):
+        smc2.smc2_prior_init(ctx.h, model, w.S, w.N, w.seed, theta[:, :1].contiguous())
+    pop = smc2.population(theta, ll, g, ll, ll[:, :2].contiguous())
+    with pytest.raises(ValueError, match="logw"):
+        smc2.smc2_reweight_resample(ctx.h, model, w.S, w.N, 0.1, 0, pop, None, None, 1, w.seed,
+                                    it)
+    ctx.close()
