@@ -105,9 +105,10 @@ typedef enum { SMC2_FP64 = 0, SMC2_MIXED = 1 } smc2_precision;
 typedef enum { SMC2_SYSTEMATIC = 0, SMC2_MULTINOMIAL = 1 } smc2_resampler;
 
 typedef struct {
-  int32_t precision;     /* SMC2_FP64: every operation in FP64.  SMC2_MIXED: propagation and
-                            weighting in FP32; running log-likelihood, logsumexp, the weight
-                            prefix sum that selects ancestors and the gradient sums in FP64 */
+  int32_t precision;     /* SMC2_FP64: every operation in FP64.  SMC2_MIXED: propagation,
+                            weighting and the ESS test's sum of squared weights in FP32; running
+                            log-likelihood, logsumexp, the weight prefix sum that selects
+                            ancestors and the gradient sums in FP64 */
   int32_t resampler;     /* SMC2_SYSTEMATIC or SMC2_MULTINOMIAL (App. B) */
   double ess_frac;       /* resample after step t < T iff ESS < ess_frac * M (Sec. II-B: 0.5) */
   int32_t ckpt_interval; /* adjoint checkpoint interval c in steps; 0 = ceil(sqrt(T_max)) */

@@ -297,6 +297,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// The FP32 sum over a wave (the mixed form's sum of squared weights, which only decides whether
+// to resample).
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f32<kDppQuadXor1>(v);
+  v += dpp_f32<kDppQuadXor2>(v);
+  v += dpp_f32<kDppRowHalfMirror>(v);
+  v += dpp_f32<kDppRowMirror>(v);
+  return (readlane_f32(v, 0) + readlane_f32(v, 16)) + (readlane_f32(v, 32) + readlane_f32(v, 48));
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave (lane order).
 __device__ __forceinline__ double wave_inclusive_sum(double v) {
   v += dpp_f64<kDppRowShr1>(0.0, v);

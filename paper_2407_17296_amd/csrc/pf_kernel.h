@@ -200,7 +200,7 @@ __device__ __forceinline__ void filter_uniforms(int j0, uint32_t fid, uint32_t c
 // resampling rule is stated in.  When M is a power of two (FAST), division by M and
 // multiplication by 1/M are the same exact operation.
 struct SysTargets {
-  double nu, Md, inv_Md, tot, inv_tot;
+  double nu, Md, inv_Md, tot, inv_tot, scale;  // scale = M / tot
   int M;
   template <bool FAST>
   __device__ double at(int i) const {
@@ -233,7 +233,7 @@ struct SysTargets {
   // The estimate alone: floor(z) + 1, and whether z lies within kTieMargin of an integer (then
   // upto must decide).
   __device__ int estimate(double P, bool &near) const {
-    const double z = P * inv_tot * Md - nu, fz = floor(z), fr = z - fz;
+    const double z = fma(P, scale, -nu), fz = floor(z), fr = z - fz;
     const int g = (int)fmin(fmax(fz + 1.0, 0.0), Md);
     near = near || !(fr > kTieMargin && fr < 1.0 - kTieMargin);
     return P < tot ? g : M;
@@ -480,7 +480,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       }
       const double inc = wave_inclusive_sum(acc);
       {
-        const double sw = readlane_f64(inc, 63), qw = wave_sum((double)qacc);
+        const double sw = readlane_f64(inc, 63), qw = (double)wave_sum(qacc);
         if (lane == 0) {
           ex[WAVES + 2 * wid] = sw;
           ex[WAVES + 2 * wid + 1] = qw;
@@ -527,6 +527,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         tg.inv_Md = 1.0 / Md;
         tg.tot = tot;
         tg.inv_tot = 1.0 / tot;
+        tg.scale = tg.inv_tot * Md;
         if (M == MP)
           systematic_ancestors<true, WAVES, PPL>(tg, base, ew, j0, M, sh_mark, sh_imax, a,
                                                  MP + lane);
