@@ -187,7 +187,8 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
  * theta_new = theta + (gamma^2 / 2) * grad_logpost + p_{k-1}.
  *   theta, grad_logpost dev [S][N][D] FP64 in;  theta_new, p_prev dev [S][N][D] FP64 out.
  *   gamma > 0.  random_walk = 1 drops the gradient term (the SMC0 proposal N(theta, gamma^2 I)).
- * Errors: SMC2_E_INVALID_ARG for NULL pointers, sizes < 1, gamma <= 0. */
+ * The context must be reserved (it names the device).
+ * Errors: SMC2_E_INVALID_ARG for an unreserved context, NULL pointers, sizes < 1, gamma <= 0. */
 smc2_status smc2_langevin_move(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,
                                double gamma, int32_t random_walk, const double *theta,
                                const double *grad_logpost, uint64_t seed,
@@ -226,13 +227,18 @@ typedef struct {
  *   estimate dev [S][2][D] FP64 out (may be NULL): the realised estimates of E[theta] and
  *   E[theta^2] (elementwise) under the normalised weights, before resampling (eq.
  *   realised_estimates with eq. normalise_smc2); NaN for a series whose weights are all zero.
- *   recycle dev [S][1 + 2D] FP64 in/out (may be NULL): running sums over iterations of
- *   l_k = ESS_k (eq. recycling_I), l_k E[theta] and l_k E[theta^2]; the recycled estimate
- *   (Sec. III-C, constants of eq. opt_recycling_constant) is recycle[s][1..] / recycle[s][0].
- *   The caller zeroes it before the first iteration.
+ *   recycle dev [S][1 + 4D] FP64 in/out (may be NULL): per series, [0] the running sum over
+ *   iterations of l_k = ESS_k (eq. recycling_I), [1, 2D] the running sums of l_k E[theta] and
+ *   l_k E[theta^2], and [2D + 1, 4D] the recycled estimates of E[theta] and E[theta^2]
+ *   (Sec. III-C: sum_k c_k E_k with the constants c_k = l_k / sum_j l_j of eq.
+ *   opt_recycling_constant), rewritten by every call; NaN while every l_k so far is zero.
+ *   Iterations whose weights are all zero add nothing.  The caller zeroes it before the first
+ *   iteration.
  * A series whose weights are all zero keeps its population and sets the device status word
  * to SMC2_E_NONFINITE (see smc2_ctx_device_status).
- * Errors: SMC2_E_INVALID_ARG for NULL pointers, N > 4096, sizes < 1, gamma <= 0. */
+ * Errors: SMC2_E_INVALID_ARG for an unreserved context, NULL pointers, N > 4096, sizes < 1,
+ * S * N above the reservation, gamma <= 0, or a model whose kind, d_x or D differs from the
+ * reservation's (the context's gather scratch is laid out for the reserved D). */
 smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,
                                    double gamma, int32_t random_walk, smc2_population *cur,
                                    const smc2_population *prev, const double *p_prev,
@@ -246,15 +252,22 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
 /* theta_1 ~ prior (eq. init_sample with q_1 = prior): theta[s][i][p] = prior_mu[p] +
  * prior_sd[p] * z with z normal number p of the PRIOR stream of sample s*N+i (iteration 1), or,
  * for a uniform parameter, prior_mu[p] + (prior_sd[p] - prior_mu[p]) * u with u uniform number p
- * of the same stream.  theta dev [S][N][D] out. */
+ * of the same stream.  theta dev [S][N][D] out.  The context must be reserved (it names the
+ * device).  Errors: SMC2_E_INVALID_ARG for an unreserved context, sizes < 1 or a NULL theta. */
 smc2_status smc2_prior_init(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,
                             uint64_t seed, double *theta, void *stream);
 
-/* Copy the resampling trace of item (s, i) from the last smc2_pf_loglik_grad call made with
- * persistent = 0: flags host [T_len[s]] (1 where the filter resampled after step t) and
- * ancestors host [T_len[s]][M] (-1 rows where it did not).  Synchronises `stream`. */
+/* Copy the trace of item (s, i) from the last smc2_pf_loglik_grad call made with
+ * persistent = 0: flags host [T_len[s]] (1 where the filter resampled after step t), ancestors
+ * host [T_len[s]][M] (-1 rows where it did not) and, if steps_s is not NULL, steps_s host
+ * [T_len[s]] FP64: the per-step log normalisers s_t = log sum_j W_{t-1}^j g(y_t | x_t^j) with
+ * the normalised weights W_{t-1} (eq. likelihood_pf_ taken step by step; their sum over t is
+ * the returned log-likelihood).  For a filter whose weights all became zero (loglik = -inf) no
+ * entry is written.  Synchronises `stream`.
+ * Errors: SMC2_E_INVALID_ARG for an unreserved or persistent context, an item out of range or
+ * NULL flags / ancestors. */
 smc2_status smc2_pf_trace(smc2_ctx *ctx, int32_t s, int32_t i, uint8_t *flags,
-                          int32_t *ancestors, void *stream);
+                          int32_t *ancestors, double *steps_s, void *stream);
 
 /* Counter-contract probe: out[r][0..3] = Philox4x32-10 words for counter ctr[r][0..3] under
  * `seed`; normals[r] = normal number n[r] and uniforms[r] = uniform number n[r] of stream
@@ -270,7 +283,9 @@ smc2_status smc2_philox_probe(int32_t R, const uint32_t *ctr, const uint32_t *n,
 smc2_status smc2_tile_info(int32_t tile, int32_t d_x, int32_t *max_particles, int32_t *waves,
                            int32_t *per_lane);
 
-/* Library version string.  0.2: smc2_model carries prior_kind and constants (the SIR model). */
+/* Library version string.  0.2: smc2_model carries prior_kind and constants (the SIR model).
+ * 0.3: the recycle row of smc2_reweight_resample also holds the recycled estimate, and
+ * smc2_pf_trace returns the per-step log normalisers. */
 const char *smc2_version(void);
 
 #ifdef __cplusplus

@@ -57,46 +57,68 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        ip = ctypes.POINTER(ctypes.c_int32)
-        u8p = ctypes.POINTER(ctypes.c_uint8)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        mp = ctypes.POINTER(_Model)
-        op = ctypes.POINTER(_PFOpts)
-        u64, u32, i32, i64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int64
-        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.orc_normal.argtypes = [u64, u32, u32, u32, u32]
-        L.orc_normal.restype = ctypes.c_double
-        L.orc_uniform.argtypes = [u64, u32, u32, u32, u32]
-        L.orc_uniform.restype = ctypes.c_double
-        L.orc_normals.argtypes = [u64, u32, u32, u32, u32, i64, dp]
-        L.orc_uniforms.argtypes = [u64, u32, u32, u32, u32, i64, dp]
-        L.orc_filter_normal.argtypes = [u64, u32, u32, u32, u32]
-        L.orc_filter_normal.restype = ctypes.c_double
-        L.orc_filter_uniform.argtypes = [u64, u32, u32, u32, u32, u32]
-        L.orc_filter_uniform.restype = ctypes.c_double
-        L.orc_resample_lower_bound.argtypes = [i32, dp, dp, ip]
-        L.orc_pf.argtypes = [mp, op, dp, i32, dp, i32, u64, u32, u32, dp, dp, ip, u8p, dp]
-        L.orc_pf.restype = ctypes.c_int
-        L.orc_pf_complex_step.argtypes = [mp, op, dp, i32, dp, i32, u64, u32, u32, i32,
-                                          ctypes.c_double, dp, dp, ip]
-        L.orc_pf_complex_step.restype = ctypes.c_int
-        L.orc_kalman.argtypes = [mp, dp, i32, dp, dp, dp]
-        L.orc_kalman.restype = ctypes.c_int
-        L.orc_log_prior.argtypes = [mp, dp, dp]
-        L.orc_log_prior.restype = ctypes.c_double
-        L.orc_langevin_move.argtypes = [i32, ctypes.c_double, dp, dp, dp, dp, dp]
-        L.orc_lkernel_log_ratio.argtypes = [i32, ctypes.c_double, dp, dp, dp]
-        L.orc_lkernel_log_ratio.restype = ctypes.c_double
-        L.orc_realised_estimate.argtypes = [i32, i32, dp, dp, dp, dp]
-        L.orc_realised_estimate.restype = ctypes.c_double
-        L.orc_recycle.argtypes = [i32, i32, dp, dp, dp]
-        L.orc_smc2_run.argtypes = [mp, op, ctypes.POINTER(_SMC2Opts), i32, dp, dp, dp, dp, dp, dp,
-                                   ip, ip, dp, dp]
-        L.orc_smc2_run.restype = ctypes.c_int
-        _lib = L
+        _lib = _configure(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def build_variant(path, replacements):
+    """Compile a copy of the oracle with each (old, new) source replacement applied (each old
+    text must occur exactly once) into `path` and load it: tests plant mistakes this way to show
+    that a pin catches them."""
+    with open(SRC_PATH) as f:
+        src = f.read()
+    for old, new in replacements:
+        if src.count(old) != 1:
+            raise ValueError("replacement text must occur once: %r" % old)
+        src = src.replace(old, new)
+    cpp = path + ".cpp"
+    with open(cpp, "w") as f:
+        f.write(src)
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-I" + _HERE, "-o", path, cpp])
+    return _configure(ctypes.CDLL(path))
+
+
+def _configure(L):
+    """Declare the argument and result types of every exported oracle function on L."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    mp = ctypes.POINTER(_Model)
+    op = ctypes.POINTER(_PFOpts)
+    u64, u32, i32, i64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int64
+    L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.orc_normal.argtypes = [u64, u32, u32, u32, u32]
+    L.orc_normal.restype = ctypes.c_double
+    L.orc_uniform.argtypes = [u64, u32, u32, u32, u32]
+    L.orc_uniform.restype = ctypes.c_double
+    L.orc_normals.argtypes = [u64, u32, u32, u32, u32, i64, dp]
+    L.orc_uniforms.argtypes = [u64, u32, u32, u32, u32, i64, dp]
+    L.orc_filter_normal.argtypes = [u64, u32, u32, u32, u32]
+    L.orc_filter_normal.restype = ctypes.c_double
+    L.orc_filter_uniform.argtypes = [u64, u32, u32, u32, u32, u32]
+    L.orc_filter_uniform.restype = ctypes.c_double
+    L.orc_resample_lower_bound.argtypes = [i32, dp, dp, ip]
+    L.orc_pf.argtypes = [mp, op, dp, i32, dp, i32, u64, u32, u32, dp, dp, ip, u8p, dp]
+    L.orc_pf.restype = ctypes.c_int
+    L.orc_pf_complex_step.argtypes = [mp, op, dp, i32, dp, i32, u64, u32, u32, i32,
+                                      ctypes.c_double, dp, dp, ip]
+    L.orc_pf_complex_step.restype = ctypes.c_int
+    L.orc_kalman.argtypes = [mp, dp, i32, dp, dp, dp]
+    L.orc_kalman.restype = ctypes.c_int
+    L.orc_log_prior.argtypes = [mp, dp, dp]
+    L.orc_log_prior.restype = ctypes.c_double
+    L.orc_langevin_move.argtypes = [i32, ctypes.c_double, dp, dp, dp, dp, dp]
+    L.orc_lkernel_log_ratio.argtypes = [i32, ctypes.c_double, dp, dp, dp]
+    L.orc_lkernel_log_ratio.restype = ctypes.c_double
+    L.orc_realised_estimate.argtypes = [i32, i32, dp, dp, dp, dp]
+    L.orc_realised_estimate.restype = ctypes.c_double
+    L.orc_recycle.argtypes = [i32, i32, dp, dp, dp]
+    L.orc_smc2_run.argtypes = [mp, op, ctypes.POINTER(_SMC2Opts), i32, dp, dp, dp, dp, dp, dp,
+                               ip, ip, dp, dp]
+    L.orc_smc2_run.restype = ctypes.c_int
+    return L
 
 
 def _dp(a):
@@ -159,16 +181,17 @@ def uniforms(seed, c0, c2, c3_, first, count):
     return out
 
 
-def resample_lower_bound(w, u):
+def resample_lower_bound(w, u, L=None):
     w, u = _f64(w), _f64(u)
     a = np.empty(len(w), dtype=np.int32)
-    lib().orc_resample_lower_bound(len(w), _dp(w), _dp(u), _ip(a))
+    (L or lib()).orc_resample_lower_bound(len(w), _dp(w), _dp(u), _ip(a))
     return a
 
 
 def pf(model, theta, y, M, seed, k, filter_id, resampler=SYSTEMATIC, ess_frac=0.5,
-       want_grad=True, want_trace=False):
-    """Run the oracle CRN-PF.  Returns dict(loglik, grad, ancestors, flags, s)."""
+       want_grad=True, want_trace=False, L=None):
+    """Run the oracle CRN-PF (of the library L, default the oracle itself).  Returns
+    dict(loglik, grad, ancestors, flags, s)."""
     theta = _f64(theta)
     y = _f64(y).reshape(-1)
     T = len(y) // model.dy if model.dy else 0
@@ -178,7 +201,7 @@ def pf(model, theta, y, M, seed, k, filter_id, resampler=SYSTEMATIC, ess_frac=0.
     anc = np.empty((T, M), dtype=np.int32) if want_trace else None
     flags = np.empty(T, dtype=np.uint8) if want_trace else None
     s = np.empty(T) if want_trace else None
-    rc = lib().orc_pf(model.ref, ctypes.byref(opts), _dp(theta), T, _dp(y), int(M), int(seed),
+    rc = (L or lib()).orc_pf(model.ref, ctypes.byref(opts), _dp(theta), T, _dp(y), int(M), int(seed),
                       int(k), int(filter_id), ctypes.byref(ll), _dp(grad), _ip(anc),
                       None if flags is None else flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                       _dp(s))

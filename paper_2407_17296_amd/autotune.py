@@ -2,11 +2,13 @@
 
 For a workload it times every built launch shape whose capacity fits the particle count
 (waves per workgroup x 64 x particles per lane = the next power of two >= M), a few
-checkpoint intervals (the square root of T, a few steps, every step) and both ways the adjoint
-obtains the forward's noise (stored or regenerated), each for a handful of launches timed with
-HIP events on the launch stream, and keeps the fastest.  Results are cached in a JSON file keyed by model, state and
-parameter dimension, particle count, series-length and item-count buckets, precision and device
-name, so a later run on the same device reuses them.
+checkpoint intervals (the square root of T, a few steps, every step), both ways the adjoint
+obtains the forward's noise (stored or regenerated) and both grid modes (one workgroup per item,
+or a persistent grid pulling items from an on-device queue), each for a handful of launches
+timed with HIP events on the launch stream, and keeps the fastest.  Results are cached in a JSON
+file keyed by the kernel sources, model, state and parameter dimension, particle count,
+series-length and item-count buckets, precision and device name, so a later run of the same
+library on the same device reuses them.
 """
 import json
 import os
@@ -22,6 +24,7 @@ CACHE = os.environ.get("SMC2_AUTOTUNE_CACHE",
 NUM_TILES = 18  # indices 1.. of the library's launch-shape table
 CKPT_CANDIDATES = (0, 8, 4, 1)
 NOISE_CANDIDATES = (1, 0)
+PERSISTENT_CANDIDATES = (0, 1)
 
 
 def _bucket(v):
@@ -31,12 +34,24 @@ def _bucket(v):
     return p
 
 
-VERSION = 2  # bump when the kernel changes enough to invalidate cached choices
+def kernel_sources_sha():
+    """Hash of the library's kernel sources: a cached choice made for other kernel code misses
+    the cache and is tuned again."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def key(w, precision, device_name):
-    return "|".join(str(v) for v in (VERSION, w.kind, w.d, w.D, w.M, _bucket(w.T_max),
-                                      _bucket(w.S * w.N), precision, device_name))
+    return "|".join(str(v) for v in (kernel_sources_sha(), w.kind, w.d, w.D, w.M,
+                                      _bucket(w.T_max), _bucket(w.S * w.N), precision,
+                                      device_name))
 
 
 def candidate_tiles(w):
@@ -52,12 +67,12 @@ def candidate_tiles(w):
     return out
 
 
-def time_config(w, precision, tile, ckpt, store_noise=1, reps=3, seed_theta=0):
+def time_config(w, precision, tile, ckpt, store_noise=1, reps=3, seed_theta=0, persistent=0):
     """Mean duration (s) of the fused forward+adjoint over `reps` launches."""
     dev = torch.device("cuda:0")
     model = smc2.Model.from_workload(w)
     opts = smc2.pf_opts(precision=precision, tile=tile, ckpt_interval=ckpt,
-                        store_noise=store_noise)
+                        store_noise=store_noise, persistent=persistent)
     ctx = smc2.Context(model, opts, w.S, w.N, w.M, w.T_len, w.T_max)
     try:
         rng = np.random.default_rng(seed_theta)
@@ -81,8 +96,8 @@ def time_config(w, precision, tile, ckpt, store_noise=1, reps=3, seed_theta=0):
 
 
 def tune(w, precision, reps=3, use_cache=True, verbose=False):
-    """Best (tile, ckpt, store_noise) for workload w at `precision`; returns a dict with the
-    timings."""
+    """Best (tile, ckpt, store_noise, persistent) for workload w at `precision`; returns a dict
+    with the timings of every configuration tried."""
     # the architecture name: the marketing name can read as empty (e.g. under a profiler)
     props = torch.cuda.get_device_properties(0)
     name = getattr(props, "gcnArchName", "") or torch.cuda.get_device_name(0)
@@ -101,21 +116,23 @@ def tune(w, precision, reps=3, use_cache=True, verbose=False):
     for tile in candidate_tiles(w):
         for ckpt in CKPT_CANDIDATES:
             for sn in NOISE_CANDIDATES:
-                try:
-                    s = time_config(w, precision, tile, ckpt, sn, reps=reps)
-                except smc2.SMC2Error:
-                    continue
-                trials.append((s, tile, ckpt, sn))
-                if verbose:
-                    print("[autotune] %s prec=%d tile=%d ckpt=%d noise=%d: %.3f ms" % (
-                        w.name, precision, tile, ckpt, sn, 1e3 * s), flush=True)
+                for pers in PERSISTENT_CANDIDATES:
+                    try:
+                        s = time_config(w, precision, tile, ckpt, sn, reps=reps, persistent=pers)
+                    except smc2.SMC2Error:
+                        continue
+                    trials.append((s, tile, ckpt, sn, pers))
+                    if verbose:
+                        print("[autotune] %s prec=%d tile=%d ckpt=%d noise=%d persistent=%d: "
+                              "%.3f ms" % (w.name, precision, tile, ckpt, sn, pers, 1e3 * s),
+                              flush=True)
     if not trials:
         raise RuntimeError("no launch shape could run workload %s" % w.name)
-    s, tile, ckpt, sn = min(trials)
-    res = dict(tile=int(tile), ckpt=int(ckpt), store_noise=int(sn), seconds=float(s),
-               trials=len(trials), tuning_seconds=time.perf_counter() - t0,
-               all=[dict(tile=int(t), ckpt=int(c), store_noise=int(n), ms=1e3 * v)
-                    for v, t, c, n in sorted(trials)])
+    s, tile, ckpt, sn, pers = min(trials)
+    res = dict(tile=int(tile), ckpt=int(ckpt), store_noise=int(sn), persistent=int(pers),
+               seconds=float(s), trials=len(trials), tuning_seconds=time.perf_counter() - t0,
+               all=[dict(tile=int(t), ckpt=int(c), store_noise=int(n), persistent=int(p),
+                         ms=1e3 * v) for v, t, c, n, p in sorted(trials)])
     if use_cache:
         cache[k] = res
         try:

@@ -172,14 +172,28 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
       }
     }
     __syncthreads();
+    // recycle row of the series: [0] sum of l_k, [1, 2D] the l_k-weighted sums, [2D + 1, 4D]
+    // the recycled estimate sum_k c_k f_k with c_k = l_k / sum_j l_j; every value is read
+    // before any is written (the barrier below), so thread 0's update of the sum of l_k does not
+    // race with the others' reads of it
+    double *rc = A.recycle ? A.recycle + (size_t)s * (4 * D + 1) : nullptr;
+    double l_new = 0.0, sum_new = 0.0;
     if (tid < 2 * D) {
       double v = 0.0;
       for (int w = 0; w < WAVES; ++w) v += sh_est[w][tid];
       v = (mx == kNegInf) ? __builtin_nan("") : v / S;
       if (A.estimate) A.estimate[(size_t)s * 2 * D + tid] = v;
-      if (A.recycle && ess > 0.0) A.recycle[(size_t)s * (2 * D + 1) + 1 + tid] += ess * v;
+      if (rc) {
+        l_new = rc[0] + ess;
+        sum_new = ess > 0.0 ? rc[1 + tid] + ess * v : rc[1 + tid];
+      }
     }
-    if (tid == 0 && A.recycle) A.recycle[(size_t)s * (2 * D + 1)] += ess;
+    __syncthreads();
+    if (rc && tid < 2 * D) {
+      rc[1 + tid] = sum_new;
+      rc[1 + 2 * D + tid] = l_new > 0.0 ? sum_new / l_new : __builtin_nan("");
+      if (tid == 0) rc[0] = l_new;
+    }
   }
   if (tid == 0) {
     if (A.ess_out) A.ess_out[s] = ess;

@@ -72,6 +72,7 @@ struct PFArgs {
   void *seg_buf;        // [slots][ckpt][rows][ld] (R): x before the step (DX rows), the noise
                         // (DX rows, only without `noise`), the normalised weight (1 row)
   void *noise;          // [slots][t_ld+1][DX][ld] (R) forward noise for the adjoint, or NULL
+  double *steps_s;      // [slots][t_ld] the per-step log normalisers s_t (a trace), or NULL
   double mconst[4];     // model constants (the SIR model's N_pop, I_0, s_e^2, s_y)
 };
 
@@ -573,6 +574,18 @@ void pf_fwd_adj_kernel(PFArgs A) {
     // loglik = sum_t max_t + sum over resampled steps and T of log S_t; the adjoint's per-step
     // log normaliser max_t + log S_t replaces S_t in LDS
     __syncthreads();  // S_t, max_t and the flags written by thread 0 are visible
+    if (A.steps_s) {
+      // the trace of s_t = log sum_j W_{t-1}^j g_t^j with normalised W_{t-1} (eq.
+      // likelihood_pf_ step by step): the carry into step t was normalised at t = 1 and after a
+      // resampling step, and otherwise sums to S_{t-1}
+      double *so = A.steps_s + (size_t)slot * A.t_ld;
+      for (int t = 1 + tid; t <= T; t += NT) {
+        double v = (double)sh_mx[t - 1] + log(sh_s[t - 1]);
+        if (t > 1 && !sh_f[t - 2]) v -= log(sh_s[t - 2]);
+        so[t - 1] = v;
+      }
+      __syncthreads();  // every S_t is read before the loop below overwrites it
+    }
     {
       double part = 0.0;
       for (int t = 1 + tid; t <= T; t += NT) {

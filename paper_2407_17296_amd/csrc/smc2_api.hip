@@ -181,7 +181,7 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 struct Layout {
   int MP, c, nseg, slots;
-  size_t anc, flags, ckpt, seg, noise, outer, total;
+  size_t anc, flags, ckpt, seg, noise, steps, outer, total;
 };
 
 }  // namespace
@@ -201,6 +201,7 @@ struct smc2_ctx {
   int32_t *anc = nullptr;
   uint8_t *flags = nullptr;
   void *ckpt = nullptr, *seg = nullptr, *noise = nullptr;
+  double *steps_s = nullptr;
   double *outer_scratch = nullptr;
   uint32_t *queue = nullptr;
   int32_t *status = nullptr;
@@ -215,7 +216,7 @@ struct smc2_ctx {
     (void)hipSetDevice(cur);
     T_len_dev = order_dev = anc = status = nullptr;
     flags = nullptr;
-    outer_scratch = nullptr;
+    outer_scratch = steps_s = nullptr;
     ckpt = seg = noise = nullptr;
     queue = nullptr;
     reserved = false;
@@ -270,8 +271,9 @@ smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, in
   L.seg = o->want_grad ? al((size_t)L.slots * L.c * (2 * dx + 1) * L.MP * rs) : 256;
   L.noise = (o->want_grad && o->store_noise)
                 ? al((size_t)L.slots * (Tc + 1) * dx * L.MP * rs) : 256;
+  L.steps = al((size_t)L.slots * Tc * 8);
   L.outer = al((size_t)items * (2 * m->D + 2) * 8);
-  L.total = L.anc + L.flags + L.ckpt + L.seg + L.noise + L.outer + al(items * 4) * 2 +
+  L.total = L.anc + L.flags + L.ckpt + L.seg + L.noise + L.steps + L.outer + al(items * 4) * 2 +
             al((size_t)S * 4) + 512;
   return SMC2_OK;
 }
@@ -297,7 +299,7 @@ int grid_slots_for(smc2_ctx *ctx, const smc2_model *m, const smc2_pf_opts *o, in
 
 extern "C" {
 
-const char *smc2_version(void) { return "smc2-mi355x 0.2 (gfx950)"; }
+const char *smc2_version(void) { return "smc2-mi355x 0.3 (gfx950)"; }
 
 const char *smc2_last_error(void) { return g_err.c_str(); }
 
@@ -391,6 +393,7 @@ smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_
   GRAB(L.ckpt, ctx->ckpt, void *);
   GRAB(L.seg, ctx->seg, void *);
   GRAB(L.noise, ctx->noise, void *);
+  GRAB(L.steps, ctx->steps_s, double *);
   GRAB(L.outer, ctx->outer_scratch, double *);
   GRAB(items * 4, ctx->order_dev, int32_t *);
   GRAB((size_t)S * 4, ctx->T_len_dev, int32_t *);
@@ -508,6 +511,7 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
   a.ckpt_buf = ctx->ckpt;
   a.seg_buf = ctx->seg;
   a.noise = (opts->want_grad && opts->store_noise) ? ctx->noise : nullptr;
+  a.steps_s = ctx->steps_s;
   model_constants(model, a.mconst);
   int grid = items;
   if (opts->persistent) {
@@ -524,7 +528,7 @@ smc2_status smc2_langevin_move(smc2_ctx *ctx, const smc2_model *model, int32_t S
                                const double *grad_logpost, uint64_t seed,
                                const uint32_t *iteration, double *theta_new, double *p_prev,
                                void *stream) {
-  if (!ctx) return fail(SMC2_E_INVALID_ARG, "ctx is NULL");
+  if (!ctx || !ctx->reserved) return fail(SMC2_E_INVALID_ARG, "context not reserved");
   std::string why;
   if (!model_ok(model, why)) return fail(SMC2_E_INVALID_ARG, why);
   if (S < 1 || N < 1 || !(gamma > 0) || !std::isfinite(gamma))
@@ -550,6 +554,8 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
   if (!ctx || !ctx->reserved) return fail(SMC2_E_INVALID_ARG, "context not reserved");
   std::string why;
   if (!model_ok(model, why)) return fail(SMC2_E_INVALID_ARG, why);
+  if (model->kind != ctx->model.kind || model->d_x != ctx->model.d_x || model->D != ctx->model.D)
+    return fail(SMC2_E_INVALID_ARG, "model differs from the reservation");
   if (S < 1 || N < 1 || N > kOuterMaxN || !(gamma > 0) || !std::isfinite(gamma))
     return fail(SMC2_E_INVALID_ARG, "need 1 <= N <= 4096, S >= 1 and gamma > 0");
   if ((long)S * N > (long)ctx->S * ctx->N)
@@ -601,7 +607,7 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
 
 smc2_status smc2_prior_init(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,
                             uint64_t seed, double *theta, void *stream) {
-  if (!ctx) return fail(SMC2_E_INVALID_ARG, "ctx is NULL");
+  if (!ctx || !ctx->reserved) return fail(SMC2_E_INVALID_ARG, "context not reserved");
   std::string why;
   if (!model_ok(model, why)) return fail(SMC2_E_INVALID_ARG, why);
   if (S < 1 || N < 1 || !theta) return fail(SMC2_E_INVALID_ARG, "bad sizes or NULL theta");
@@ -614,7 +620,7 @@ smc2_status smc2_prior_init(smc2_ctx *ctx, const smc2_model *model, int32_t S, i
 }
 
 smc2_status smc2_pf_trace(smc2_ctx *ctx, int32_t s, int32_t i, uint8_t *flags,
-                          int32_t *ancestors, void *stream) {
+                          int32_t *ancestors, double *steps_s, void *stream) {
   if (!ctx || !ctx->reserved) return fail(SMC2_E_INVALID_ARG, "context not reserved");
   if (ctx->opts.persistent)
     return fail(SMC2_E_INVALID_ARG, "traces are kept per item only without persistence");
@@ -626,6 +632,8 @@ smc2_status smc2_pf_trace(smc2_ctx *ctx, int32_t s, int32_t i, uint8_t *flags,
   const size_t slot = (size_t)s * ctx->N + i;
   const size_t t_ld = std::max(ctx->T_max, 1), ld = ctx->L.MP;
   if (T == 0) return SMC2_OK;
+  if (steps_s)
+    HIP_TRY(hipMemcpy(steps_s, ctx->steps_s + slot * t_ld, (size_t)T * 8, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(flags, ctx->flags + slot * t_ld, T, hipMemcpyDeviceToHost));
   std::vector<int32_t> rows((size_t)T * ld);
   HIP_TRY(hipMemcpy(rows.data(), ctx->anc + slot * t_ld * ld, rows.size() * 4,

@@ -64,7 +64,7 @@ class SMC2Run:
         self.anc = torch.zeros((S, N), dtype=torch.int32, device=self.dev)
         self.ess = torch.zeros(S, **f64)
         self.estimate = torch.zeros((S, 2, D), **f64)
-        self.recycle = torch.zeros((S, 1 + 2 * D), **f64)
+        self.recycle = torch.zeros((S, 1 + 4 * D), **f64)
         self.resampled = torch.zeros(S, dtype=torch.int32, device=self.dev)
         self._cur_c = smc2.population(**self.cur)
         self._prev_c = smc2.population(**self.prev)
@@ -139,10 +139,10 @@ class SMC2Run:
                     estimate=self.estimate.cpu().numpy())
 
     def recycled_estimate(self):
-        """Recycled E[theta], E[theta^2] over the iterations so far (Sec. III-C), [S][2][D]."""
-        r = self.recycle.cpu().numpy()
+        """Recycled E[theta], E[theta^2] over the iterations so far (Sec. III-C), [S][2][D], as
+        the reweighting kernel left them in the recycle rows."""
         D = self.w.D
-        return (r[:, 1:] / r[:, :1]).reshape(-1, 2, D)
+        return self.recycle[:, 1 + 2 * D:].cpu().numpy().reshape(-1, 2, D)
 
     def close(self):
         self.graph = None

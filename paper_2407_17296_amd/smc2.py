@@ -74,7 +74,7 @@ SIGNATURES = [
                                               _I32, _U64, _VP, _I32, _VP, _VP, _VP, _VP, _VP,
                                               _VP]),
     ("smc2_prior_init", ctypes.c_int, [_VP, _MP, _I32, _I32, _U64, _VP, _VP]),
-    ("smc2_pf_trace", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP, _VP]),
+    ("smc2_pf_trace", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP, _VP, _VP]),
     ("smc2_philox_probe", ctypes.c_int, [_I32, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("smc2_tile_info", ctypes.c_int, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                       ctypes.POINTER(_I32)]),
@@ -258,7 +258,7 @@ def smc2_reweight_resample(ctx, model, S, N, gamma, random_walk, cur, prev, p_pr
         _ptr(ancestors, torch.int32, "ancestors", SN), _ptr(ess, torch.float64, "ess", int(S)),
         _ptr(resampled, torch.int32, "resampled", int(S)),
         _ptr(estimate, torch.float64, "estimate", int(S) * 2 * D),
-        _ptr(recycle, torch.float64, "recycle", int(S) * (1 + 2 * D)), _stream(stream)),
+        _ptr(recycle, torch.float64, "recycle", int(S) * (1 + 4 * D)), _stream(stream)),
         "smc2_reweight_resample")
 
 
@@ -269,12 +269,18 @@ def smc2_prior_init(ctx, model, S, N, seed, theta, stream=None):
            "smc2_prior_init")
 
 
-def smc2_pf_trace(ctx, s, i, T, M, stream=None):
+def smc2_pf_trace(ctx, s, i, T, M, stream=None, with_steps=False):
+    """(flags [T], ancestors [T][M]) of item (s, i), and with with_steps the per-step log
+    normalisers s_t [T] as a third element."""
     flags = np.zeros(max(T, 1), dtype=np.uint8)
     anc = np.full((max(T, 1), M), -1, dtype=np.int32)
+    st = np.full(max(T, 1), np.nan) if with_steps else None
     _check(lib().smc2_pf_trace(ctx, int(s), int(i), flags.ctypes.data_as(ctypes.c_void_p),
-                               anc.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
-           "smc2_pf_trace")
+                               anc.ctypes.data_as(ctypes.c_void_p),
+                               None if st is None else st.ctypes.data_as(ctypes.c_void_p),
+                               _stream(stream)), "smc2_pf_trace")
+    if with_steps:
+        return flags[:T], anc[:T], st[:T]
     return flags[:T], anc[:T]
 
 
@@ -342,6 +348,9 @@ class PFLogLik(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx_, theta, y, context, seed, iteration):
+        if not context.opts.want_grad:
+            raise ValueError("PFLogLik needs a context reserved with want_grad = 1: the backward "
+                             "returns the gradient the forward kernel computes")
         S, N, D = context.S, context.N, context.model.D
         loglik = torch.empty((S, N), dtype=torch.float64, device=theta.device)
         grad = torch.empty((S, N, D), dtype=torch.float64, device=theta.device)

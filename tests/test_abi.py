@@ -147,3 +147,17 @@ def test_sir_tiles_are_built(lib):
         assert mp == 64 * w * p
     with pytest.raises(smc2.SMC2Error):
         smc2.smc2_tile_info(8, 2)  # 16 particles per lane is not built for two components
+
+
+def test_calls_without_a_reserved_context_are_refused(lib):
+    """The outer-step calls take their device from a reserved context and refuse a missing one
+    with a status, before touching any device."""
+    m = smc2.Model(smc2.LG1D, 1, 3)
+    mp = ctypes.byref(m.c)
+    assert lib.smc2_langevin_move(None, mp, 1, 4, 0.1, 0, None, None, 1, None, None, None,
+                                  None) == smc2.SMC2_E_INVALID_ARG
+    assert lib.smc2_prior_init(None, mp, 1, 4, 1, None, None) == smc2.SMC2_E_INVALID_ARG
+    assert lib.smc2_reweight_resample(None, mp, 1, 4, 0.1, 0, None, None, None, 1, 1, None, 0,
+                                      None, None, None, None, None,
+                                      None) == smc2.SMC2_E_INVALID_ARG
+    assert b"reserved" in lib.smc2_last_error()

@@ -38,3 +38,27 @@ def test_binding_refuses_buffers_smaller_than_the_sizes():
         smc2.smc2_reweight_resample(ctx.h, model, w.S, w.N, 0.1, 0, pop, None, None, 1, w.seed,
                                     it)
     ctx.close()
+
+
+def test_outer_step_refuses_a_model_other_than_the_reserved_one():
+    """The reweighting call's gather scratch is laid out for the reserved model's D: a model of
+    another kind or dimension is refused on the host."""
+    import torch
+    from paper_2407_17296_amd import synth
+    w = synth.make(0, N=4)
+    model = smc2.Model.from_workload(w)
+    ctx = smc2.Context(model, smc2.pf_opts(), w.S, w.N, w.M, w.T_len, w.T_max)
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    other = smc2.Model(smc2.LG_DIAG, 16, 18)
+    D = other.D
+    theta = torch.zeros((w.S, w.N, D), **f64)
+    g = torch.zeros((w.S, w.N, D), **f64)
+    ll = torch.zeros((w.S, w.N), **f64)
+    it = torch.ones(1, dtype=torch.int32, device=dev)
+    pop = smc2.population(theta, ll.clone(), g, ll.clone(), ll.clone())
+    with pytest.raises(smc2.SMC2Error, match="reservation") as e:
+        smc2.smc2_reweight_resample(ctx.h, other, w.S, w.N, 0.1, 0, pop, None, None, 1, w.seed,
+                                    it)
+    assert e.value.status == smc2.SMC2_E_INVALID_ARG
+    ctx.close()
