@@ -693,6 +693,16 @@ void orc_langevin_move(int32_t D, double gamma, const double *theta, const doubl
   }
 }
 
+void orc_random_walk_move(int32_t D, double gamma, const double *theta, const double *xi,
+                          double *theta_new, double *p_prev) {
+  /* SMC0 proposal N(theta, Gamma), Gamma = gamma^2 I (Sec. III-D), with the same velocity
+   * p_{k-1} = gamma xi; it uses no gradient, and its kernel is symmetric */
+  for (int p = 0; p < D; ++p) {
+    p_prev[p] = gamma * xi[p];
+    theta_new[p] = theta[p] + p_prev[p];
+  }
+}
+
 double orc_lkernel_log_ratio(int32_t D, double gamma, const double *grad_prev,
                              const double *grad_new, const double *p_prev) {
   /* L(theta_{k-1} | theta_k) / q(theta_k | theta_{k-1}) for the one-step Langevin dynamics
@@ -789,11 +799,8 @@ int orc_smc2_run(const orc_model *mdl, const orc_pf_opts *pf, const orc_smc2_opt
         if (so->proposal == 1) {
           orc_langevin_move(D, so->gamma, &th[i * D], &gpi[i * D], xi.data(), &thn[i * D],
                             &pprev[i * D]);
-        } else { /* SMC0: N(theta, Gamma) */
-          for (int p = 0; p < D; ++p) {
-            pprev[i * D + p] = so->gamma * xi[p];
-            thn[i * D + p] = th[i * D + p] + pprev[i * D + p];
-          }
+        } else {
+          orc_random_walk_move(D, so->gamma, &th[i * D], xi.data(), &thn[i * D], &pprev[i * D]);
         }
       }
     }

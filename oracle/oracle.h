@@ -111,6 +111,9 @@ double orc_log_prior(const orc_model *mdl, const double *theta, double *grad /* 
 /* Langevin move with velocity p_{k-1} = gamma * xi: theta_new = theta + (gamma^2/2) g + p. */
 void orc_langevin_move(int32_t D, double gamma, const double *theta, const double *grad_logpost,
                        const double *xi, double *theta_new, double *p_prev);
+/* Random-walk move (SMC0) with the same velocity: theta_new = theta + gamma xi, p = gamma xi. */
+void orc_random_walk_move(int32_t D, double gamma, const double *theta, const double *xi,
+                          double *theta_new, double *p_prev);
 /* Incremental log L-kernel/proposal ratio of the Langevin proposal,
  * log N(-p_k; 0, G) - log N(p_{k-1}; 0, G), with p_k = p_{k-1} + F(theta_{k-1}) + F(theta_k). */
 double orc_lkernel_log_ratio(int32_t D, double gamma, const double *grad_prev,

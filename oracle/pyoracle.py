@@ -110,6 +110,7 @@ def _configure(L):
     L.orc_log_prior.argtypes = [mp, dp, dp]
     L.orc_log_prior.restype = ctypes.c_double
     L.orc_langevin_move.argtypes = [i32, ctypes.c_double, dp, dp, dp, dp, dp]
+    L.orc_random_walk_move.argtypes = [i32, ctypes.c_double, dp, dp, dp, dp]
     L.orc_lkernel_log_ratio.argtypes = [i32, ctypes.c_double, dp, dp, dp]
     L.orc_lkernel_log_ratio.restype = ctypes.c_double
     L.orc_realised_estimate.argtypes = [i32, i32, dp, dp, dp, dp]
@@ -251,6 +252,14 @@ def langevin_move(gamma, theta, grad_logpost, xi):
     D = len(theta)
     tn, pp = np.zeros(D), np.zeros(D)
     lib().orc_langevin_move(D, float(gamma), _dp(theta), _dp(g), _dp(xi), _dp(tn), _dp(pp))
+    return tn, pp
+
+
+def random_walk_move(gamma, theta, xi):
+    theta, xi = _f64(theta), _f64(xi)
+    D = len(theta)
+    tn, pp = np.zeros(D), np.zeros(D)
+    lib().orc_random_walk_move(D, float(gamma), _dp(theta), _dp(xi), _dp(tn), _dp(pp))
     return tn, pp
 
 

@@ -51,6 +51,37 @@ def oracle_pf(oracle, w, theta, s, i, k=1, resampler=smc2.SYSTEMATIC, ess_frac=0
                      resampler=resampler, ess_frac=ess_frac, want_trace=want_trace)
 
 
+def oracle_batch(oracle, w, theta, items, k, want_grad=True, threads=None):
+    """The oracle's filter on each (s, i) of `items` at theta[s, i] (their own random streams),
+    on a pool of host threads; returns (loglik [len(items)], grad [len(items)][D] or None)."""
+    import concurrent.futures as cf
+    import os
+    m = oracle_model(oracle, w)
+    threads = threads or max(1, min(16, os.cpu_count() or 1))
+
+    def one(si):
+        s, i = si
+        r = oracle.pf(m, theta[s, i], w.y[s, :w.T_len[s]], w.M, w.seed, k, s * w.N + i,
+                      want_grad=want_grad)
+        return r["loglik"], r["grad"]
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        out = list(ex.map(one, items))
+    ll = np.array([o[0] for o in out])
+    g = np.array([o[1] for o in out]) if want_grad else None
+    return ll, g
+
+
+def paired_mean_zero(d, what):
+    """Paired differences d [n] or [n][D] have mean zero within 4 standard errors; returns the
+    mean and its standard error."""
+    d = np.asarray(d, dtype=float)
+    mean = d.mean(axis=0)
+    se = d.std(axis=0, ddof=1) / np.sqrt(d.shape[0])
+    assert np.all(np.abs(mean) <= 4 * se + 1e-12), (what, mean, se)
+    return mean, se
+
+
 def oracle_sensitivity(oracle, w, theta, s, i, k, eps, resampler=0, ess_frac=0.5, reps=2):
     """The oracle at theta[s, i], and how far its own answer moves when theta is perturbed by a
     relative eps in random sign directions (eps = unit roundoff of the working precision).
@@ -88,5 +119,5 @@ def spread_theta(w, scale=0.5, seed=0):
     return w.theta_true + scale * rng.standard_normal((w.S, w.N, w.D))
 
 
-__all__ = ["say", "gpu_pf", "oracle_model", "oracle_pf", "oracle_sensitivity", "rel_err", "spread_theta",
-           "synth"]
+__all__ = ["say", "gpu_pf", "oracle_model", "oracle_pf", "oracle_batch", "oracle_sensitivity",
+           "paired_mean_zero", "rel_err", "spread_theta", "synth"]

@@ -5,7 +5,7 @@ form -- ancestors bit-exact, log-likelihood relative error <= 1e-12, gradient re
 import numpy as np
 import pytest
 
-from gpu_util import gpu_pf, rel_err, say, spread_theta
+from gpu_util import gpu_pf, oracle_batch, paired_mean_zero, rel_err, say, spread_theta
 from paper_2407_17296_amd import smc2, synth
 from test_gpu_pf_parity import _check_fp64, _mixed_report
 
@@ -84,22 +84,19 @@ def test_mixed_sir_within_tolerance(oracle):
     assert all(r[2] for r in same)
 
 
-def test_mixed_and_fp64_sir_estimate_the_same_likelihood():
-    """N independent filters at the data-generating rates: the paired differences of loglik and
-    gradient between the mixed and the FP64 form have mean zero within 4 standard errors."""
+def test_mixed_sir_and_oracle_estimate_the_same_likelihood(oracle):
+    """N independent filters at the data-generating rates, each paired with the oracle's filter
+    on its own stream: the paired differences of loglik and gradient between the mixed form and
+    the oracle have mean zero within 4 standard errors."""
     w = _sir(N=512)
     theta = np.broadcast_to(w.theta_true, (1, w.N, w.D)).copy()
-    l64, g64, _ = gpu_pf(w, theta, precision=smc2.FP64, k=7)
     l32, g32, _ = gpu_pf(w, theta, precision=smc2.MIXED, k=7)
-    d = (l32 - l64)[0]
-    se = d.std(ddof=1) / np.sqrt(len(d))
-    dg = (g32 - g64)[0]
-    seg = dg.std(axis=0, ddof=1) / np.sqrt(len(d))
-    say("  SIR loglik mean fp64 %.4f (sd %.3f); paired diff %.2e +- %.2e; grad diff %s +- %s" % (
-        l64.mean(), l64.std(), d.mean(), se, np.array2string(dg.mean(axis=0), precision=3),
+    lo, go = oracle_batch(oracle, w, theta, [(0, i) for i in range(w.N)], 7)
+    m, se = paired_mean_zero(l32[0] - lo, "loglik")
+    mg, seg = paired_mean_zero(g32[0] - go, "grad")
+    say("  SIR loglik mean oracle %.4f (sd %.3f); paired diff %.2e +- %.2e; grad diff %s +- %s" % (
+        lo.mean(), lo.std(), m, se, np.array2string(mg, precision=3),
         np.array2string(seg, precision=3)))
-    assert abs(d.mean()) <= 4 * se + 1e-9
-    assert np.all(np.abs(dg.mean(axis=0)) <= 4 * seg + 1e-9)
 
 
 def test_sir_stored_and_regenerated_noise_agree():

@@ -68,12 +68,14 @@ def test_log_prior_is_gaussian(oracle):
 
 
 @pytest.mark.slow
-def test_no_data_posterior_is_the_prior(oracle):
+@pytest.mark.parametrize("proposal", [1, 0])
+def test_no_data_posterior_is_the_prior(oracle, proposal):
     """T = 0: pi = prior N(0, I); the filter returns l = 0 and grad = 0, so SMC^2 with the
-    Langevin proposal and its L-kernel must keep the prior's moments."""
+    Langevin proposal and its L-kernel (proposal 1), or with the random walk and its symmetric
+    kernel (proposal 0, SMC0), must keep the prior's moments."""
     m = oracle.Model(oracle.LG1D, 1, 3)
     N, K, gamma = 4096, 6, 0.7
-    rec = oracle.smc2_run(m, np.zeros((0, 1)), N, 4, K, gamma, seed=123)
+    rec = oracle.smc2_run(m, np.zeros((0, 1)), N, 4, K, gamma, seed=123, proposal=proposal)
     assert np.all(rec["loglik"] == 0.0)
     for k in range(K):
         lw = rec["logw"][k]
@@ -186,3 +188,24 @@ def test_recycling_constants(oracle):
     assert np.allclose(oracle.recycle([7.0], est[:1]), est[0], rtol=1e-14)
     l = np.array([1.0, 3.0, 6.0])
     assert np.allclose(oracle.recycle(l, est), (l[:, None] * est).sum(0) / l.sum(), rtol=1e-14)
+
+
+def test_random_walk_move_is_the_smc0_proposal(oracle):
+    """SMC0 proposes N(theta, gamma^2 I) (Sec. III-D): over 4096 moves with the move stream's
+    normals, (theta_new - theta) / gamma is standard normal (KS), independent of theta, and the
+    velocity equals the step."""
+    rng = np.random.default_rng(4)
+    gamma, N, D = 0.175, 4096, 3
+    c3 = oracle.c3(5, oracle.MOVE_NORMAL)
+    steps, thetas = [], []
+    for i in range(N):
+        th = rng.standard_normal(D) * 2.0
+        xi = [oracle.lib().orc_normal(99, 0xFFFFFFFF, i, c3, p) for p in range(D)]
+        tn, pp = oracle.random_walk_move(gamma, th, xi)
+        assert np.array_equal(pp, tn - th) or np.allclose(pp, tn - th, rtol=1e-15, atol=1e-15)
+        steps.append((tn - th) / gamma)
+        thetas.append(th)
+    z, th = np.array(steps), np.array(thetas)
+    assert stats.kstest(z.ravel(), "norm").pvalue > 1e-4
+    for p in range(D):
+        assert abs(np.corrcoef(z[:, p], th[:, p])[0, 1]) < 5 / np.sqrt(N)
