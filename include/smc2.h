@@ -247,6 +247,27 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
                                    int32_t *ancestors, double *ess, int32_t *resampled,
                                    double *estimate, double *recycle, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): smc2_reweight_resample without a context.  It takes
+ * the same arguments with the same meaning, layout and ownership, except that the device is the
+ * calling thread's current HIP device and the status word is the caller's: status dev int32
+ * out (may be NULL), set to SMC2_E_NONFINITE when some series has every weight zero (the caller
+ * zeroes it; nothing resets it).  The gather scratch is a fixed array of 2^20 doubles (8 MiB)
+ * in the library's device image, which every GPU the library runs on holds until the process
+ * ends; the call allocates nothing.  Every call on a GPU shares that GPU's array, so calls that
+ * overlap on one GPU (concurrent streams, or threads) race and must be ordered by the caller.
+ * The array's contents need no clearing between calls.
+ * Errors: those of smc2_reweight_resample without the reservation checks, and
+ * SMC2_E_INVALID_ARG when S * N * (2D + 2) exceeds 2^20. */
+smc2_status smc2_reweight_resample_noalloc(const smc2_model *model, int32_t S, int32_t N,
+                                           double gamma, int32_t random_walk,
+                                           smc2_population *cur, const smc2_population *prev,
+                                           const double *p_prev, int32_t first_iteration,
+                                           uint64_t seed, uint32_t *iteration,
+                                           int32_t advance_iteration, int32_t *ancestors,
+                                           double *ess, int32_t *resampled, double *estimate,
+                                           double *recycle, int32_t *status, void *stream);
+
 /* ---- initialisation and inspection ------------------------------------------------------- */
 
 /* theta_1 ~ prior (eq. init_sample with q_1 = prior): theta[s][i][p] = prior_mu[p] +

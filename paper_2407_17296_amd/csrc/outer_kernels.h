@@ -66,9 +66,10 @@ struct OuterArgs {
   double *ess_out;
   int32_t *resampled_out;
   double *estimate;  // [S][2][D] realised E[theta], E[theta^2] of this iteration, or NULL
-  double *recycle;   // [S][1 + 2D] running sums (l, l E[theta], l E[theta^2]), or NULL
+  double *recycle;   // [S][1 + 4D] running sums (l, l E[theta], l E[theta^2]) and the
+                     // recycled estimate, or NULL
   double *scratch;  // [S][N][2D+2] gather double buffer
-  int32_t *status;
+  int32_t *status;  // device status word, or NULL
 };
 
 // K3: one workgroup of kOuterThreads threads per series (N <= 4096); sample i belongs to thread
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(kOuterThreads) void reweight_resample_kernel(OuterA
   if (tid == 0) {
     if (A.ess_out) A.ess_out[s] = ess;
     if (A.resampled_out) A.resampled_out[s] = res ? 1 : 0;
-    if (mx == kNegInf) *A.status = 5;  // every weight of this series is zero
+    if (mx == kNegInf && A.status) *A.status = 5;  // every weight of this series is zero
   }
   if (!res) {
     if (A.anc_out)

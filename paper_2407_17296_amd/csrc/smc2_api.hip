@@ -179,6 +179,17 @@ const PFKernel *find_kernel(int model, int precision, int tile) {
 
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
+// Gather scratch of smc2_reweight_resample_noalloc: a file-scope device array that every GPU the
+// library runs on holds until the process ends (8 MiB: S * N * (2D + 2) doubles).  Host code
+// never passes the array's name to a kernel (on the host it is only a stand-in for the symbol):
+// its device address is looked up once per device and kept in g_noalloc_scratch.
+constexpr size_t kNoAllocScratchDoubles = (size_t)1 << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxDevices = 64;
+void *g_noalloc_scratch[kMaxDevices];
+std::once_flag g_noalloc_once[kMaxDevices];
+hipError_t g_noalloc_err[kMaxDevices];
+
 struct Layout {
   int MP, c, nseg, slots;
   size_t anc, flags, ckpt, seg, noise, steps, outer, total;
@@ -544,29 +555,37 @@ smc2_status smc2_langevin_move(smc2_ctx *ctx, const smc2_model *model, int32_t S
   return SMC2_OK;
 }
 
-smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,
-                                   double gamma, int32_t random_walk, smc2_population *cur,
-                                   const smc2_population *prev, const double *p_prev,
-                                   int32_t first_iteration, uint64_t seed,
-                                   uint32_t *iteration, int32_t advance_iteration,
-                                   int32_t *ancestors, double *ess, int32_t *resampled,
-                                   double *estimate, double *recycle, void *stream) {
-  if (!ctx || !ctx->reserved) return fail(SMC2_E_INVALID_ARG, "context not reserved");
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by smc2_reweight_resample and its no-allocation variant.
+smc2_status check_reweight_args(const smc2_model *model, int32_t S, int32_t N, double gamma,
+                                int32_t random_walk, const smc2_population *cur,
+                                const smc2_population *prev, const double *p_prev,
+                                int32_t first_iteration, const uint32_t *iteration) {
   std::string why;
   if (!model_ok(model, why)) return fail(SMC2_E_INVALID_ARG, why);
-  if (model->kind != ctx->model.kind || model->d_x != ctx->model.d_x || model->D != ctx->model.D)
-    return fail(SMC2_E_INVALID_ARG, "model differs from the reservation");
   if (S < 1 || N < 1 || N > kOuterMaxN || !(gamma > 0) || !std::isfinite(gamma))
     return fail(SMC2_E_INVALID_ARG, "need 1 <= N <= 4096, S >= 1 and gamma > 0");
-  if ((long)S * N > (long)ctx->S * ctx->N)
-    return fail(SMC2_E_INVALID_ARG, "S*N exceeds the reservation");
   if (!cur || !cur->theta || !cur->logpost || !cur->grad_logpost || !cur->loglik || !cur->logw ||
       !iteration)
     return fail(SMC2_E_INVALID_ARG, "cur population or iteration has a NULL pointer");
   if (!first_iteration && (!prev || !prev->logpost || !prev->logw ||
                            (!random_walk && (!prev->grad_logpost || !p_prev))))
     return fail(SMC2_E_INVALID_ARG, "prev population or p_prev has a NULL pointer");
-  DeviceGuard g(ctx->device);
+  return SMC2_OK;
+}
+
+// The reweighting kernel's launch (and the iteration counter's advance) on `hs`, with the gather
+// scratch and the status word given.
+smc2_status launch_reweight(const smc2_model *model, int32_t S, int32_t N, double gamma,
+                            int32_t random_walk, smc2_population *cur,
+                            const smc2_population *prev, const double *p_prev,
+                            int32_t first_iteration, uint64_t seed, uint32_t *iteration,
+                            int32_t advance_iteration, int32_t *ancestors, double *ess,
+                            int32_t *resampled, double *estimate, double *recycle,
+                            double *gather, int32_t *status, hipStream_t hs) {
   OuterArgs a{};
   a.S = S;
   a.N = N;
@@ -593,9 +612,8 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
   a.resampled_out = resampled;
   a.estimate = estimate;
   a.recycle = recycle;
-  a.scratch = ctx->outer_scratch;
-  a.status = ctx->status;
-  hipStream_t hs = (hipStream_t)stream;
+  a.scratch = gather;
+  a.status = status;
   hipLaunchKernelGGL(reweight_resample_kernel, dim3(S), dim3(kOuterThreads), 0, hs, a);
   HIP_TRY(hipGetLastError());
   if (advance_iteration) {
@@ -603,6 +621,64 @@ smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32
     HIP_TRY(hipGetLastError());
   }
   return SMC2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+smc2_status smc2_reweight_resample(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,
+                                   double gamma, int32_t random_walk, smc2_population *cur,
+                                   const smc2_population *prev, const double *p_prev,
+                                   int32_t first_iteration, uint64_t seed,
+                                   uint32_t *iteration, int32_t advance_iteration,
+                                   int32_t *ancestors, double *ess, int32_t *resampled,
+                                   double *estimate, double *recycle, void *stream) {
+  if (!ctx || !ctx->reserved) return fail(SMC2_E_INVALID_ARG, "context not reserved");
+  smc2_status st = check_reweight_args(model, S, N, gamma, random_walk, cur, prev, p_prev,
+                                       first_iteration, iteration);
+  if (st != SMC2_OK) return st;
+  if (model->kind != ctx->model.kind || model->d_x != ctx->model.d_x || model->D != ctx->model.D)
+    return fail(SMC2_E_INVALID_ARG, "model differs from the reservation");
+  if ((long)S * N > (long)ctx->S * ctx->N)
+    return fail(SMC2_E_INVALID_ARG, "S*N exceeds the reservation");
+  DeviceGuard g(ctx->device);
+  return launch_reweight(model, S, N, gamma, random_walk, cur, prev, p_prev, first_iteration,
+                         seed, iteration, advance_iteration, ancestors, ess, resampled, estimate,
+                         recycle, ctx->outer_scratch, ctx->status, (hipStream_t)stream);
+}
+
+smc2_status smc2_reweight_resample_noalloc(const smc2_model *model, int32_t S, int32_t N,
+                                           double gamma, int32_t random_walk,
+                                           smc2_population *cur, const smc2_population *prev,
+                                           const double *p_prev, int32_t first_iteration,
+                                           uint64_t seed, uint32_t *iteration,
+                                           int32_t advance_iteration, int32_t *ancestors,
+                                           double *ess, int32_t *resampled, double *estimate,
+                                           double *recycle, int32_t *status, void *stream) {
+  smc2_status st = check_reweight_args(model, S, N, gamma, random_walk, cur, prev, p_prev,
+                                       first_iteration, iteration);
+  if (st != SMC2_OK) return st;
+  if ((size_t)S * (size_t)N * (size_t)(2 * model->D + 2) > kNoAllocScratchDoubles)
+    return fail(SMC2_E_INVALID_ARG,
+                "S * N * (2D + 2) = " + std::to_string((size_t)S * N * (2 * model->D + 2)) +
+                    " exceeds the no-allocation scratch of " +
+                    std::to_string(kNoAllocScratchDoubles) + " doubles");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SMC2_E_UNSUPPORTED, "device index above 63");
+  // once per device, with that device current: the device address of the scratch array
+  std::call_once(g_noalloc_once[dev], [dev] {
+    void *p = nullptr;
+    g_noalloc_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_noalloc_scratch[dev] = g_noalloc_err[dev] == hipSuccess ? p : nullptr;
+  });
+  if (g_noalloc_err[dev] != hipSuccess || !g_noalloc_scratch[dev])
+    return fail(SMC2_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                   hipGetErrorString(g_noalloc_err[dev]));
+  return launch_reweight(model, S, N, gamma, random_walk, cur, prev, p_prev, first_iteration,
+                         seed, iteration, advance_iteration, ancestors, ess, resampled, estimate,
+                         recycle, (double *)g_noalloc_scratch[dev], status, (hipStream_t)stream);
 }
 
 smc2_status smc2_prior_init(smc2_ctx *ctx, const smc2_model *model, int32_t S, int32_t N,

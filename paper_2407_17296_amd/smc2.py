@@ -73,6 +73,9 @@ SIGNATURES = [
     ("smc2_reweight_resample", ctypes.c_int, [_VP, _MP, _I32, _I32, _D, _I32, _POP, _POP, _VP,
                                               _I32, _U64, _VP, _I32, _VP, _VP, _VP, _VP, _VP,
                                               _VP]),
+    ("smc2_reweight_resample_noalloc", ctypes.c_int, [_MP, _I32, _I32, _D, _I32, _POP, _POP,
+                                                      _VP, _I32, _U64, _VP, _I32, _VP, _VP, _VP,
+                                                      _VP, _VP, _VP, _VP]),
     ("smc2_prior_init", ctypes.c_int, [_VP, _MP, _I32, _I32, _U64, _VP, _VP]),
     ("smc2_pf_trace", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP, _VP, _VP]),
     ("smc2_philox_probe", ctypes.c_int, [_I32, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -260,6 +263,28 @@ def smc2_reweight_resample(ctx, model, S, N, gamma, random_walk, cur, prev, p_pr
         _ptr(estimate, torch.float64, "estimate", int(S) * 2 * D),
         _ptr(recycle, torch.float64, "recycle", int(S) * (1 + 4 * D)), _stream(stream)),
         "smc2_reweight_resample")
+
+
+def smc2_reweight_resample_noalloc(model, S, N, gamma, random_walk, cur, prev, p_prev,
+                                   first_iteration, seed, iteration, advance_iteration=0,
+                                   ancestors=None, ess=None, resampled=None, estimate=None,
+                                   recycle=None, status=None, stream=None):
+    SN, D = int(S) * int(N), int(model.c.D)
+    _check_population(cur, SN, D, "cur")
+    if prev is not None and not first_iteration:
+        _check_population(prev, SN, D, "prev")
+    _check(lib().smc2_reweight_resample_noalloc(
+        ctypes.byref(model.c), int(S), int(N), float(gamma), int(random_walk),
+        ctypes.byref(cur), None if prev is None else ctypes.byref(prev),
+        _ptr(p_prev, torch.float64, "p_prev", None if first_iteration else SN * D),
+        int(first_iteration), int(seed),
+        _ptr(iteration, torch.int32, "iteration", 1), int(advance_iteration),
+        _ptr(ancestors, torch.int32, "ancestors", SN), _ptr(ess, torch.float64, "ess", int(S)),
+        _ptr(resampled, torch.int32, "resampled", int(S)),
+        _ptr(estimate, torch.float64, "estimate", int(S) * 2 * D),
+        _ptr(recycle, torch.float64, "recycle", int(S) * (1 + 4 * D)),
+        _ptr(status, torch.int32, "status", 1), _stream(stream)),
+        "smc2_reweight_resample_noalloc")
 
 
 def smc2_prior_init(ctx, model, S, N, seed, theta, stream=None):
