@@ -41,8 +41,9 @@
 // The parameter adjoint is accumulated in FP64 per thread (for states of a multiple of four
 // components: per wave, in LDS) and reduced once per item.
 //
-// The series y, the per-step log normalisers s_t and the resampling flags of the current item
-// live in LDS (dynamic shared memory sized by the longest series).
+// The series y of the current item lives in LDS (dynamic shared memory sized by the longest
+// series); the per-step sums S_t (later the log normalisers), maxima and resampling flags in the
+// slot's global scratch.
 #pragma once
 
 #include "device_common.h"
@@ -60,7 +61,7 @@ struct PFArgs {
   int32_t S, N, M, T_max, ckpt, nseg_max;
   int32_t ld;           // particle stride of the per-slot scratch (>= particles per workgroup)
   int32_t t_ld;         // step stride of the per-slot scratch (>= every T_len)
-  int32_t lds_T;        // steps held in LDS (>= every T_len)
+  int32_t lds_T;        // steps of y held in LDS (>= every T_len)
   int32_t resampler, want_grad, n_items, persistent;
   double ess_thresh;    // ess_frac * M
   uint64_t seed;
@@ -73,15 +74,17 @@ struct PFArgs {
                         // (DX rows, only without `noise`), the normalised weight (1 row)
   void *noise;          // [slots][t_ld+1][DX][ld] (R) forward noise for the adjoint, or NULL
   double *steps_s;      // [slots][t_ld] the per-step log normalisers s_t (a trace), or NULL
+  double *step_scr;     // [slots][2][t_ld]: S_t (after the sweep max_t + log S_t), max_t
   double mconst[4];     // model constants (the SIR model's N_pop, I_0, s_e^2, s_y)
 };
 
-// Dynamic shared memory of one item: y as R [lds_T * DY], then S_t (later max_t + log S_t) as
-// double [lds_T], then max_t as R [lds_T], then the flags as bytes [lds_T].
+// Dynamic shared memory of one item: y as R [lds_T * DY].  The per-step scalars (S_t, max_t and
+// the resampling flag), which one thread writes once per step and the adjoint reads once per
+// step, live in the slot's global scratch instead, so that a long series does not take LDS that
+// would otherwise hold more resident workgroups.
 template <typename R, int DY>
 __host__ __device__ constexpr size_t pf_dyn_lds_bytes(int lds_T) {
-  return ((size_t)lds_T * DY * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T * 8 +
-         ((size_t)lds_T * sizeof(R) + 7) / 8 * 8 + (size_t)lds_T;
+  return ((size_t)lds_T * DY * sizeof(R) + 7) / 8 * 8;
 }
 
 // The filter's noise (counter contract): element g = j*DX + q of step t (t = 0: the initial
@@ -318,9 +321,6 @@ void pf_fwd_adj_kernel(PFArgs A) {
   __shared__ int sh_item;
   extern __shared__ double sh_dyn[];
   R *sh_y = (R *)sh_dyn;
-  double *sh_s = sh_dyn + ((size_t)A.lds_T * DY * sizeof(R) + 7) / 8;
-  R *sh_mx = (R *)(sh_s + A.lds_T);
-  uint8_t *sh_f = (uint8_t *)(sh_s + A.lds_T + ((size_t)A.lds_T * sizeof(R) + 7) / 8);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
@@ -379,6 +379,9 @@ void pf_fwd_adj_kernel(PFArgs A) {
     R *ck = (R *)A.ckpt_buf + (size_t)slot * A.nseg_max * (DX + 1) * LD;
     int32_t *anc = A.anc + (size_t)slot * A.t_ld * LD;
     uint8_t *flg = A.flags + (size_t)slot * A.t_ld;
+    // per-step scalars of the item: S_t (max_t + log S_t once the sweep is done) and max_t
+    double *g_s = A.step_scr + (size_t)slot * 2 * A.t_ld;
+    double *g_mx = g_s + A.t_ld;
     R *nz = A.noise ? (R *)A.noise + (size_t)slot * (A.t_ld + 1) * DX * LD : nullptr;
     __syncthreads();  // y staged, markers cleared
 
@@ -498,9 +501,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
       const bool res = (t < T) && (S * S < A.ess_thresh * Q);  // ESS = S^2 / Q (eq. ess)
       lw_uniform = res && !kWide;
       if (tid == 0) {
-        sh_s[t - 1] = S;
-        sh_mx[t - 1] = mxR;
-        sh_f[t - 1] = res ? 1 : 0;
+        g_s[t - 1] = S;
+        g_mx[t - 1] = mx;
         flg[t - 1] = res ? 1 : 0;
       }
       if (!res) continue;
@@ -580,8 +582,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
       // resampling step, and otherwise sums to S_{t-1}
       double *so = A.steps_s + (size_t)slot * A.t_ld;
       for (int t = 1 + tid; t <= T; t += NT) {
-        double v = (double)sh_mx[t - 1] + log(sh_s[t - 1]);
-        if (t > 1 && !sh_f[t - 2]) v -= log(sh_s[t - 2]);
+        double v = g_mx[t - 1] + log(g_s[t - 1]);
+        if (t > 1 && !flg[t - 2]) v -= log(g_s[t - 2]);
         so[t - 1] = v;
       }
       __syncthreads();  // every S_t is read before the loop below overwrites it
@@ -589,9 +591,9 @@ void pf_fwd_adj_kernel(PFArgs A) {
     {
       double part = 0.0;
       for (int t = 1 + tid; t <= T; t += NT) {
-        const double lS = log(sh_s[t - 1]), m = (double)sh_mx[t - 1];
-        part += (t == T || sh_f[t - 1]) ? m + lS : m;
-        sh_s[t - 1] = m + lS;
+        const double lS = log(g_s[t - 1]), m = g_mx[t - 1];
+        part += (t == T || flg[t - 1]) ? m + lS : m;
+        g_s[t - 1] = m + lS;
       }
       double v[1] = {part};
       block_sum_vec<WAVES, 1>(v, sh_vec);
@@ -663,7 +665,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
     auto reverse_step = [&](int t, const R (&xp)[PPL][DX], const R (&ce)[PPL][DX],
                             const R (&cw)[PPL], const int (&ca)[PPL]) {
       const R *yv = sh_y + (size_t)(t - 1) * DY;
-      const bool res = t < T && sh_f[t - 1] != 0;
+      const bool res = t < T && flg[t - 1] != 0;
       if (t == T) {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
@@ -707,7 +709,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         // the step and its weight rebuilt, and the step differentiated
         for (int t = T; t >= 1; --t) {
           const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
-          const bool res = t < T && sh_f[t - 1] != 0;
+          const bool res = t < T && flg[t - 1] != 0;
           const bool need_w = t == T || res;
           R cl[PPL];
           int ca[PPL];
@@ -718,7 +720,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
           mdl.per_step(t);
           const R *yv = sh_y + (size_t)(t - 1) * DY;
-          const R st = (R)sh_s[t - 1];  // max_t + log S_t
+          const R st = (R)g_s[t - 1];  // max_t + log S_t
           R tp[NP];
 #pragma unroll
           for (int k = 0; k < NP; ++k) tp[k] = (R)0;
@@ -750,13 +752,13 @@ void pf_fwd_adj_kernel(PFArgs A) {
       int na[PPL];
       auto load_trace = [&](int t) {
         const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
-        const bool lres = t < T && sh_f[t - 1] != 0;
+        const bool lres = t < T && flg[t - 1] != 0;
 #pragma unroll
         for (int q = 0; q < DX; ++q) {
           load_comp<PPL>(cks + q * LD + j0, nx, q);
           if (nz) load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ne, q);
         }
-        if (t > 1 && sh_f[t - 2] == 0)
+        if (t > 1 && flg[t - 2] == 0)
           load_run<PPL>(cks + DX * LD + j0, nl);
         else
 #pragma unroll
@@ -786,8 +788,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
         if (!nz) filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, ce);
         mdl.per_step(t);
         const R *yv = sh_y + (size_t)(t - 1) * DY;
-        const bool need_w = t == T || sh_f[t - 1] != 0;
-        const R st = (R)sh_s[t - 1];  // max_t + log S_t
+        const bool need_w = t == T || flg[t - 1] != 0;
+        const R st = (R)g_s[t - 1];  // max_t + log S_t
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
           cw[p] = (R)0;
@@ -815,7 +817,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         const R *cks = ck + (size_t)seg * (DX + 1) * LD;
 #pragma unroll
         for (int q = 0; q < DX; ++q) load_comp<PPL>(cks + q * LD + j0, x, q);
-        if (kWide || (t0 > 0 && sh_f[t0 - 1] == 0))
+        if (kWide || (t0 > 0 && flg[t0 - 1] == 0))
           load_run<PPL>(cks + DX * LD + j0, lW);
         else
 #pragma unroll
@@ -824,7 +826,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         R ne[PPL][DX];
         if (nz) load_noise(t0 + 1, ne);
         for (int t = t0 + 1; t <= t1; ++t) {
-          const bool res = sh_f[t - 1] != 0;
+          const bool res = flg[t - 1] != 0;
           int a[PPL];
           if (res) load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, a);
           R e[PPL][DX];
@@ -840,7 +842,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
           mdl.per_step(t);
           const R *yv = sh_y + (size_t)(t - 1) * DY;
           R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
-          const R st = (R)sh_s[t - 1], mt = sh_mx[t - 1];  // max_t + log S_t, max_t
+          const R st = (R)g_s[t - 1], mt = (R)g_mx[t - 1];  // max_t + log S_t, max_t
           R wv[PPL];
 #pragma unroll
           for (int q = 0; q < DX; ++q) {
@@ -881,7 +883,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         int na[PPL];
         auto load_step = [&](int t) {
           const R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
-          const bool lres = t < T && sh_f[t - 1] != 0;
+          const bool lres = t < T && flg[t - 1] != 0;
 #pragma unroll
           for (int q = 0; q < DX; ++q) {
             load_comp<PPL>(row + q * LD + j0, nx, q);

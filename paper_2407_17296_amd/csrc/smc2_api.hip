@@ -192,7 +192,7 @@ hipError_t g_noalloc_err[kMaxDevices];
 
 struct Layout {
   int MP, c, nseg, slots;
-  size_t anc, flags, ckpt, seg, noise, steps, outer, total;
+  size_t anc, flags, ckpt, seg, noise, steps, stepscr, outer, total;
 };
 
 }  // namespace
@@ -212,7 +212,7 @@ struct smc2_ctx {
   int32_t *anc = nullptr;
   uint8_t *flags = nullptr;
   void *ckpt = nullptr, *seg = nullptr, *noise = nullptr;
-  double *steps_s = nullptr;
+  double *steps_s = nullptr, *step_scr = nullptr;
   double *outer_scratch = nullptr;
   uint32_t *queue = nullptr;
   int32_t *status = nullptr;
@@ -227,7 +227,7 @@ struct smc2_ctx {
     (void)hipSetDevice(cur);
     T_len_dev = order_dev = anc = status = nullptr;
     flags = nullptr;
-    outer_scratch = steps_s = nullptr;
+    outer_scratch = steps_s = step_scr = nullptr;
     ckpt = seg = noise = nullptr;
     queue = nullptr;
     reserved = false;
@@ -283,9 +283,10 @@ smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, in
   L.noise = (o->want_grad && o->store_noise)
                 ? al((size_t)L.slots * (Tc + 1) * dx * L.MP * rs) : 256;
   L.steps = al((size_t)L.slots * Tc * 8);
+  L.stepscr = al((size_t)L.slots * 2 * Tc * 8);
   L.outer = al((size_t)items * (2 * m->D + 2) * 8);
-  L.total = L.anc + L.flags + L.ckpt + L.seg + L.noise + L.steps + L.outer + al(items * 4) * 2 +
-            al((size_t)S * 4) + 512;
+  L.total = L.anc + L.flags + L.ckpt + L.seg + L.noise + L.steps + L.stepscr + L.outer +
+            al(items * 4) * 2 + al((size_t)S * 4) + 512;
   return SMC2_OK;
 }
 
@@ -405,6 +406,7 @@ smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_
   GRAB(L.seg, ctx->seg, void *);
   GRAB(L.noise, ctx->noise, void *);
   GRAB(L.steps, ctx->steps_s, double *);
+  GRAB(L.stepscr, ctx->step_scr, double *);
   GRAB(L.outer, ctx->outer_scratch, double *);
   GRAB(items * 4, ctx->order_dev, int32_t *);
   GRAB((size_t)S * 4, ctx->T_len_dev, int32_t *);
@@ -523,6 +525,7 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
   a.seg_buf = ctx->seg;
   a.noise = (opts->want_grad && opts->store_noise) ? ctx->noise : nullptr;
   a.steps_s = ctx->steps_s;
+  a.step_scr = ctx->step_scr;
   model_constants(model, a.mconst);
   int grid = items;
   if (opts->persistent) {
