@@ -77,8 +77,15 @@ def algorithmic_bytes_per_particle_step(r, c, rs, d=1, lw_skip=True):
     """HBM bytes the method must move per particle-step: the int32 ancestor written in the
     forward and read in the adjoint at a resampled step (fraction r), and the checkpoint written
     and read once every c steps (rs bytes per value): the state, and the carried log-weight
-    unless the step before resampled (then every log-weight is -log M and none is stored)."""
-    return r * 8.0 + 2.0 * (d + (1.0 - r if lw_skip else 1.0)) * rs / c
+    unless the step before resampled (then every log-weight is -log M and none is stored); with
+    a checkpoint every step, the carried log-weight only where the adjoint rebuilds the step's
+    weights, at a resampled step (a fraction r of the steps after a step that did not
+    resample)."""
+    if c == 1 and lw_skip:
+        lw = (1.0 - r) * r
+    else:
+        lw = 1.0 - r if lw_skip else 1.0
+    return r * 8.0 + 2.0 * (d + lw) * rs / c
 
 
 def design_bytes_per_particle_step(r, c, rs, store_noise, d=1, lw_skip=True):

@@ -280,6 +280,10 @@ __device__ __forceinline__ float readlane_f32(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// A lane's value in the arithmetic type (lane index uniform across the wave).
+__device__ __forceinline__ float readlane_r(float v, int lane) { return readlane_f32(v, lane); }
+__device__ __forceinline__ double readlane_r(double v, int lane) { return readlane_f64(v, lane); }
+
 __device__ __forceinline__ float wave_max(float v) {
   v = fmaxf(v, dpp_f32<kDppQuadXor1>(v));
   v = fmaxf(v, dpp_f32<kDppQuadXor2>(v));

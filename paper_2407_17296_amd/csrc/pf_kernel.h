@@ -10,7 +10,9 @@
 // kappa_i = sum_j [nu_i > c_j]), with systematic u_i = (i + nu)/M or multinomial u_i = nu_i;
 // equal weights after.  The int32 ancestors are stored, and (x, log W) checkpoints are stored
 // every c steps (log W only where the step before did not resample: after a resampling step
-// every log-weight is -log M, which the adjoint takes from the step's flag).
+// every log-weight is -log M, which the adjoint takes from the step's flag; with a checkpoint at
+// every step, log W only where the adjoint rebuilds the step's normalised weights, at a
+// resampled step or at T).
 //
 // The log-sum-exp takes two workgroup exchanges per step: the maximum, then the FP64 sums of
 // exp(lw - max) (the total of a lane prefix scan that resampling reuses) and of their squares.
@@ -314,6 +316,9 @@ void pf_fwd_adj_kernel(PFArgs A) {
   __shared__ double sh_P[MP];        // multinomial prefix
   __shared__ R sh_X[2][MP];          // gather / adjoint-scatter staging (ping-pong)
   __shared__ int sh_mark[MP + 64];   // systematic first-offspring markers + a dummy per lane
+  // with a checkpoint at every step, the carried log-weights into the step wait here until the
+  // step decides whether the adjoint will need them (each lane reads back only its own slots)
+  __shared__ __align__(16) R sh_lw[kWide ? 1 : MP];
   __shared__ double sh_ex[2][3 * WAVES];  // per-wave max and (sum, sum of squares), ping-pong
   __shared__ double sh_vec[WAVES * NP];
   __shared__ double sh_tb[kWide ? WAVES * NP : 1];  // per-wave parameter adjoint (wide states)
@@ -413,16 +418,28 @@ void pf_fwd_adj_kernel(PFArgs A) {
     // a checkpoint then stores the state only, and the adjoint takes the constant (not for wide
     // states, whose checkpoints are mostly state and whose registers are scarce)
     bool lw_uniform = !kWide;
+    // With a checkpoint at every step the adjoint needs the carry into step t only where it
+    // rebuilds the normalised weights, at a resampled step or at T: the carry waits in LDS and
+    // reaches HBM only there (and only if it is not the uniform -log M).
+    const bool lazy_lw = c == 1 && !kWide;
     // the systematic resampling words of 64 consecutive steps, one per lane (drawn by the
     // vector unit once per 64 steps instead of by the scalar unit at every resampling step)
     uint32_t nu_word = 0;
     int nu_base = -1;
     for (int t = 1; t <= T; ++t) {
+      const bool lwu_in = lw_uniform;
       if (ck_left == 0) {
         R *cks = ck + (size_t)ck_idx * (DX + 1) * LD;
 #pragma unroll
         for (int q = 0; q < DX; ++q) store_comp<PPL>(cks + q * LD + j0, x, q);
-        if (!lw_uniform) store_run<PPL>(cks + DX * LD + j0, lW);
+        if (!lw_uniform) {
+          if (lazy_lw) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) sh_lw[j0 + p] = lW[p];
+          } else {
+            store_run<PPL>(cks + DX * LD + j0, lW);
+          }
+        }
         ck_left = c;
         ++ck_idx;
       }
@@ -500,6 +517,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
       }
       const bool res = (t < T) && (S * S < A.ess_thresh * Q);  // ESS = S^2 / Q (eq. ess)
       lw_uniform = res && !kWide;
+      if (lazy_lw && !lwu_in && (res || t == T)) {
+        R lin[PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) lin[p] = sh_lw[j0 + p];
+        store_run<PPL>(ck + (size_t)(t - 1) * (DX + 1) * LD + DX * LD + j0, lin);
+      }
       if (tid == 0) {
         g_s[t - 1] = S;
         g_mx[t - 1] = mx;
@@ -603,6 +626,31 @@ void pf_fwd_adj_kernel(PFArgs A) {
 
     // ---- adjoint --------------------------------------------------------------------------
     __syncthreads();  // the per-step log normalisers are visible to the workgroup
+    // The per-step scalars the sweeps below read at every step (resampling flag, max_t + log
+    // S_t, max_t) come from a window of 64 aligned steps, one step per lane, loaded once per 64
+    // steps: the flags as a wave ballot (with the 64 steps before the window, for the flag of
+    // the step before), the others read back with readlane.  The step index is uniform, so
+    // every read of the window is too.
+    int wbase = -(1 << 30);
+    uint64_t wfl = 0, wfl_lo = 0;
+    R wst = (R)0, wmt = (R)0;
+    auto win = [&](int t) {  // makes the scalars of steps t and t - 1 readable (1 <= t <= T)
+      const int b = (t - 1) & ~63;
+      if (b != wbase) {
+        wbase = b;
+        const int i = b + lane, il = b - 64 + lane;
+        wfl = __ballot(i < T && flg[i] != 0);
+        wfl_lo = __ballot(il >= 0 && flg[il] != 0);
+        wst = i < T ? (R)g_s[i] : (R)0;
+        wmt = i < T ? (R)g_mx[i] : (R)0;
+      }
+    };
+    auto flag_of = [&](int t) -> bool {  // step t in [wbase - 63, wbase + 64]
+      const int i = t - 1 - wbase;
+      return i >= 0 ? ((wfl >> i) & 1ull) != 0 : ((wfl_lo >> (i + 64)) & 1ull) != 0;
+    };
+    auto st_of = [&](int t) -> R { return readlane_r(wst, t - 1 - wbase); };
+    auto mt_of = [&](int t) -> R { return readlane_r(wmt, t - 1 - wbase); };
     R xb[PPL][DX], wb[PPL];
     double tb[NP];
 #pragma unroll
@@ -665,7 +713,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
     auto reverse_step = [&](int t, const R (&xp)[PPL][DX], const R (&ce)[PPL][DX],
                             const R (&cw)[PPL], const int (&ca)[PPL]) {
       const R *yv = sh_y + (size_t)(t - 1) * DY;
-      const bool res = t < T && flg[t - 1] != 0;
+      win(t);
+      const bool res = t < T && flag_of(t);
       if (t == T) {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) wb[p] = cw[p];
@@ -701,15 +750,17 @@ void pf_fwd_adj_kernel(PFArgs A) {
     };
 
     if (c == 1) {
-      // Every step's starting state (x, log W) is a checkpoint: one reverse sweep that reads
-      // the state before each step, rebuilds the step and its weight, and differentiates it.
+      // Every step's starting state is a checkpoint (its log W where the step's weights are
+      // rebuilt): one reverse sweep that reads the state before each step, rebuilds the step and
+      // its weight, and differentiates it.
       zero_staging();
       if constexpr (kWide) {
         // one particle at a time: its state before the step (checkpoint) and noise are read,
         // the step and its weight rebuilt, and the step differentiated
         for (int t = T; t >= 1; --t) {
           const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
-          const bool res = t < T && flg[t - 1] != 0;
+          win(t);
+          const bool res = t < T && flag_of(t);
           const bool need_w = t == T || res;
           R cl[PPL];
           int ca[PPL];
@@ -720,7 +771,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
           mdl.per_step(t);
           const R *yv = sh_y + (size_t)(t - 1) * DY;
-          const R st = (R)g_s[t - 1];  // max_t + log S_t
+          const R st = st_of(t);  // max_t + log S_t
           R tp[NP];
 #pragma unroll
           for (int k = 0; k < NP; ++k) tp[k] = (R)0;
@@ -750,15 +801,18 @@ void pf_fwd_adj_kernel(PFArgs A) {
       } else {
       R nx[PPL][DX], nl[PPL], ne[PPL][DX];
       int na[PPL];
+      // reads the flags of steps t and t - 1 from the window of step t or t + 1
       auto load_trace = [&](int t) {
         const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
-        const bool lres = t < T && flg[t - 1] != 0;
+        const bool lres = t < T && flag_of(t);
 #pragma unroll
         for (int q = 0; q < DX; ++q) {
           load_comp<PPL>(cks + q * LD + j0, nx, q);
           if (nz) load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ne, q);
         }
-        if (t > 1 && flg[t - 2] == 0)
+        // the carry into step t was stored only where the step's weights are rebuilt (a
+        // resampled step or T) and it was not the uniform -log M
+        if ((t == T || lres) && t > 1 && !flag_of(t - 1))
           load_run<PPL>(cks + DX * LD + j0, nl);
         else
 #pragma unroll
@@ -769,10 +823,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
           for (int p = 0; p < PPL; ++p) na[p] = 0;
       };
+      if (T > 0) win(T);
       if (kPrefetch && T > 0) load_trace(T);
       for (int t = T; t >= 1; --t) {
         R cx[PPL][DX], ce[PPL][DX], cl[PPL], cw[PPL];
         int ca[PPL];
+        win(t);
         if (!kPrefetch) load_trace(t);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
@@ -788,8 +844,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
         if (!nz) filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, ce);
         mdl.per_step(t);
         const R *yv = sh_y + (size_t)(t - 1) * DY;
-        const bool need_w = t == T || flg[t - 1] != 0;
-        const R st = (R)g_s[t - 1];  // max_t + log S_t
+        const bool need_w = t == T || flag_of(t);
+        const R st = st_of(t);  // max_t + log S_t
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
           cw[p] = (R)0;
@@ -817,7 +873,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
         const R *cks = ck + (size_t)seg * (DX + 1) * LD;
 #pragma unroll
         for (int q = 0; q < DX; ++q) load_comp<PPL>(cks + q * LD + j0, x, q);
-        if (kWide || (t0 > 0 && flg[t0 - 1] == 0))
+        if (t0 > 0) win(t0);
+        if (kWide || (t0 > 0 && !flag_of(t0)))
           load_run<PPL>(cks + DX * LD + j0, lW);
         else
 #pragma unroll
@@ -826,7 +883,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
         R ne[PPL][DX];
         if (nz) load_noise(t0 + 1, ne);
         for (int t = t0 + 1; t <= t1; ++t) {
-          const bool res = flg[t - 1] != 0;
+          win(t);
+          const bool res = flag_of(t);
           int a[PPL];
           if (res) load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, a);
           R e[PPL][DX];
@@ -842,7 +900,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
           mdl.per_step(t);
           const R *yv = sh_y + (size_t)(t - 1) * DY;
           R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
-          const R st = (R)g_s[t - 1], mt = (R)g_mx[t - 1];  // max_t + log S_t, max_t
+          const R st = st_of(t), mt = mt_of(t);  // max_t + log S_t, max_t
           R wv[PPL];
 #pragma unroll
           for (int q = 0; q < DX; ++q) {
@@ -881,9 +939,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
         // ancestors of step t - 1 are loaded while step t is processed
         R nx[PPL][DX], nw[PPL];
         int na[PPL];
+        // reads the flag of step t from the window of step t or t + 1
         auto load_step = [&](int t) {
           const R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
-          const bool lres = t < T && flg[t - 1] != 0;
+          const bool lres = t < T && flag_of(t);
 #pragma unroll
           for (int q = 0; q < DX; ++q) {
             load_comp<PPL>(row + q * LD + j0, nx, q);
@@ -901,10 +960,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) na[p] = 0;
         };
+        win(t1);
         if (kPrefetch) load_step(t1);
         for (int t = t1; t > t0; --t) {
           R cx[PPL][DX], ce[PPL][DX], cw[PPL];
           int ca[PPL];
+          win(t);
           if (!kPrefetch) load_step(t);
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
