@@ -298,7 +298,10 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
   for (int p = 0; p < PPL; ++p) a[p] = min(max(a[p], before), M - 1);
 }
 
-template <typename R, class Model, int WAVES, int PPL>
+// EVERY: a checkpoint at every step (the reverse sweep rebuilds each step from the state before
+// it); otherwise checkpoints every A.ckpt steps and segments recomputed forward.  The two are
+// separate instantiations so that neither carries the other's registers.
+template <typename R, class Model, int WAVES, int PPL, bool EVERY>
 __global__ __launch_bounds__(WAVES * 64,
                              (sizeof(R) == 4 && Model::DX == 1 && PPL <= 4 && WAVES <= 4) ? 4
                              : (sizeof(R) == 4 && Model::DX == 1 && PPL == 8)            ? 2
@@ -313,9 +316,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
   // step, so that a lane holds only its particles' states and adjoints across steps, and sum the
   // parameter adjoint per wave into LDS instead of keeping NP FP64 accumulators per lane.
   constexpr bool kWide = DX % 4 == 0;
-  __shared__ double sh_P[MP];        // multinomial prefix
+  // the multinomial prefix (MP doubles) or the systematic first-offspring markers with a dummy
+  // per lane (MP + 64 ints): a launch uses one resampler, so the two share their LDS
+  __shared__ double sh_pm[MP];
+  double *const sh_P = sh_pm;
+  int *const sh_mark = reinterpret_cast<int *>(sh_pm);
   __shared__ R sh_X[2][MP];          // gather / adjoint-scatter staging (ping-pong)
-  __shared__ int sh_mark[MP + 64];   // systematic first-offspring markers + a dummy per lane
   // with a checkpoint at every step, the carried log-weights into the step wait here until the
   // step decides whether the adjoint will need them (each lane reads back only its own slots)
   __shared__ __align__(16) R sh_lw[kWide ? 1 : MP];
@@ -338,7 +344,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
                  c3r = stream_word(k, kStreamResample);
   const double lWeq = -log(Md);
   const R lWeqR = (R)lWeq;
-  const int c = A.ckpt;
+  const int c = EVERY ? 1 : A.ckpt;
   const bool systematic = A.resampler == 0;
   const size_t LD = (size_t)A.ld;
 
@@ -421,7 +427,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
     // With a checkpoint at every step the adjoint needs the carry into step t only where it
     // rebuilds the normalised weights, at a resampled step or at T: the carry waits in LDS and
     // reaches HBM only there (and only if it is not the uniform -log M).
-    const bool lazy_lw = c == 1 && !kWide;
+    constexpr bool lazy_lw = EVERY && !kWide;
     // the systematic resampling words of 64 consecutive steps, one per lane (drawn by the
     // vector unit once per 64 steps instead of by the scalar unit at every resampling step)
     uint32_t nu_word = 0;
@@ -472,16 +478,21 @@ void pf_fwd_adj_kernel(PFArgs A) {
           mloc = fmax(mloc, v);
         }
       }
-      // log-sum-exp, exchange 1: the maximum
+      // log-sum-exp, exchange 1: the maximum (a single wave holds it already)
       double *ex = sh_ex[t & 1];
-      {
-        const double mw = (double)wave_max(mloc);
-        if (lane == 0) ex[wid] = mw;
-      }
-      __syncthreads();
-      double mx = ex[0];
+      double mx;
+      if constexpr (WAVES == 1) {
+        mx = (double)wave_max(mloc);
+      } else {
+        {
+          const double mw = (double)wave_max(mloc);
+          if (lane == 0) ex[wid] = mw;
+        }
+        __syncthreads();
+        mx = ex[0];
 #pragma unroll
-      for (int w = 1; w < WAVES; ++w) mx = fmax(mx, ex[w]);
+        for (int w = 1; w < WAVES; ++w) mx = fmax(mx, ex[w]);
+      }
       if (mx == kNegInf) {  // no particle explains y_t
         dead = true;
         break;
@@ -500,20 +511,25 @@ void pf_fwd_adj_kernel(PFArgs A) {
         lW[p] = lW[p] - mxR;  // the carry: log-weights shifted by the maximum
       }
       const double inc = wave_inclusive_sum(acc);
-      {
-        const double sw = readlane_f64(inc, 63), qw = (double)wave_sum(qacc);
-        if (lane == 0) {
-          ex[WAVES + 2 * wid] = sw;
-          ex[WAVES + 2 * wid + 1] = qw;
-        }
-      }
-      __syncthreads();
       double S = 0.0, Q = 0.0, off = 0.0;
+      if constexpr (WAVES == 1) {
+        S = readlane_f64(inc, 63);
+        Q = (double)wave_sum(qacc);
+      } else {
+        {
+          const double sw = readlane_f64(inc, 63), qw = (double)wave_sum(qacc);
+          if (lane == 0) {
+            ex[WAVES + 2 * wid] = sw;
+            ex[WAVES + 2 * wid + 1] = qw;
+          }
+        }
+        __syncthreads();
 #pragma unroll
-      for (int w = 0; w < WAVES; ++w) {
-        if (w == wid) off = S;
-        S = S + ex[WAVES + 2 * w];
-        Q = Q + ex[WAVES + 2 * w + 1];
+        for (int w = 0; w < WAVES; ++w) {
+          if (w == wid) off = S;
+          S = S + ex[WAVES + 2 * w];
+          Q = Q + ex[WAVES + 2 * w + 1];
+        }
       }
       const bool res = (t < T) && (S * S < A.ess_thresh * Q);  // ESS = S^2 / Q (eq. ess)
       lw_uniform = res && !kWide;
@@ -749,7 +765,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       pp = 0;
     };
 
-    if (c == 1) {
+    if constexpr (EVERY) {
       // Every step's starting state is a checkpoint (its log W where the step's weights are
       // rebuilt): one reverse sweep that reads the state before each step, rebuilds the step and
       // its weight, and differentiates it.

@@ -9,8 +9,10 @@ namespace smc2 {
 
 struct PFKernel {
   int model, dx, precision, waves, ppl;
+  // launch and resident workgroups per compute unit, for the every-step checkpoint sweep
+  // (every = 1) or the segment recompute
   void (*launch)(const PFArgs &, int grid, hipStream_t);
-  int (*occupancy)(int lds_T);       // resident workgroups per compute unit
+  int (*occupancy)(int lds_T, int every);
   size_t (*dyn_lds)(int lds_T);      // dynamic shared memory per workgroup
   size_t static_lds;                 // static shared memory per workgroup (upper bound)
 };
@@ -32,25 +34,32 @@ size_t dyn_lds_pf(int lds_T) {
 template <typename R, class Model, int W, int P>
 void launch_pf(const PFArgs &a, int grid, hipStream_t st) {
   const size_t dyn = pf_dyn_lds_bytes<R, Model::DY>(a.lds_T);
-  hipLaunchKernelGGL((pf_fwd_adj_kernel<R, Model, W, P>), dim3(grid), dim3(W * 64), dyn, st, a);
+  if (a.ckpt == 1)
+    hipLaunchKernelGGL((pf_fwd_adj_kernel<R, Model, W, P, true>), dim3(grid), dim3(W * 64), dyn,
+                       st, a);
+  else
+    hipLaunchKernelGGL((pf_fwd_adj_kernel<R, Model, W, P, false>), dim3(grid), dim3(W * 64), dyn,
+                       st, a);
 }
 
 template <typename R, class Model, int W, int P>
-int occupancy_pf(int lds_T) {
+int occupancy_pf(int lds_T, int every) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pf_fwd_adj_kernel<R, Model, W, P>, W * 64,
-                                                   dyn_lds_pf<R, Model, W, P>(lds_T)) !=
-          hipSuccess ||
-      n < 1)
-    n = 1;
+  const size_t dyn = dyn_lds_pf<R, Model, W, P>(lds_T);
+  const hipError_t e =
+      every ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &n, pf_fwd_adj_kernel<R, Model, W, P, true>, W * 64, dyn)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &n, pf_fwd_adj_kernel<R, Model, W, P, false>, W * 64, dyn);
+  if (e != hipSuccess || n < 1) n = 1;
   return n;
 }
 
 template <typename R, class Model, int W, int P>
 void add_entry(std::vector<PFKernel> &v, int model, int precision) {
   constexpr int MP = W * 64 * P;
-  constexpr size_t stat = MP * (sizeof(double) + 2 * sizeof(R) + sizeof(int)) +
-                          (2 * (2 * W + 2) + W * Model::NP) * sizeof(double) + 4 * W + 64;
+  constexpr size_t stat = MP * (sizeof(double) + 3 * sizeof(R)) +
+                          (2 * (2 * W + 2) + 2 * W * Model::NP) * sizeof(double) + 4 * W + 64;
   v.push_back(PFKernel{model, Model::DX, precision, W, P, &launch_pf<R, Model, W, P>,
                        &occupancy_pf<R, Model, W, P>, &dyn_lds_pf<R, Model, W, P>, stat});
 }

@@ -304,7 +304,9 @@ int grid_slots_for(smc2_ctx *ctx, const smc2_model *m, const smc2_pf_opts *o, in
   if (tile < 0) return 1;
   const PFKernel *k = find_kernel(m->kind, o->precision, tile);
   if (!k) return 1;
-  return ctx->num_cus * k->occupancy(std::max(ctx->T_max_hint, 1));
+  const int Tc = std::max(ctx->T_max_hint, 1);
+  const int c = o->ckpt_interval > 0 ? o->ckpt_interval : (int)std::ceil(std::sqrt((double)Tc));
+  return ctx->num_cus * k->occupancy(Tc, std::min(c, Tc) == 1);
 }
 
 }  // namespace
@@ -529,7 +531,8 @@ smc2_status smc2_pf_loglik_grad(smc2_ctx *ctx, const smc2_model *model, const sm
   model_constants(model, a.mconst);
   int grid = items;
   if (opts->persistent) {
-    grid = std::min(items, std::min(ctx->L.slots, ctx->num_cus * k->occupancy(a.lds_T)));
+    grid = std::min(items,
+                    std::min(ctx->L.slots, ctx->num_cus * k->occupancy(a.lds_T, a.ckpt == 1)));
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, hs, ctx->queue);
   }
   k->launch(a, grid, hs);
