@@ -146,6 +146,49 @@ struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
     }
     tb[D_X + 1] += (Acc)mulz(wb, s2 - (R)D_X);
   }
+
+  // Blockwise form, for streaming a particle through a step four components at a time
+  // (components 4b .. 4b + 3): given theta the components are independent, and log g couples
+  // them only through its sum of squared residuals.  Taking the blocks in order reproduces the
+  // sums of step / logg / logg_adj / step_adj bit for bit.
+  static constexpr bool kBlocks = true;
+  __device__ void step_block(int b, R (&x4)[4], const R (&e4)[4]) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x4[i] = fmar(A[4 * b + i], x4[i], sx * e4[i]);
+  }
+  // s2 += the block's squared residuals of log g at the state after the step
+  __device__ void resid_block(int b, const R *y, const R (&x4)[4], R &s2) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const R r = (y[4 * b + i] - x4[i]) * isy;
+      s2 = fmar(r, r, s2);
+    }
+  }
+  __device__ R logg_of(R s2) const { return fmar((R)-0.5, s2, c0); }
+  // the transposed step of a block: xb4 holds the block's state adjoint after the step on entry
+  // and before it on return; tb receives the adjoints of A_{4b..4b+3}; s2 and ssx carry the sums
+  // whose adjoints adj_finish adds once all blocks are done
+  template <typename Acc>
+  __device__ void adj_block(int b, const R *y, const R (&xp4)[4], const R (&xn4)[4],
+                            const R (&e4)[4], R wb, R (&xb4)[4], Acc *tb, R &s2, R &ssx) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const R r = (y[4 * b + i] - xn4[i]) * isy;
+      xb4[i] += mulz(wb, r * isy);
+      s2 = fmar(r, r, s2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      tb[4 * b + i] += (Acc)mulz(xb4[i], xp4[i]);
+      ssx += mulz(xb4[i], e4[i]);
+      xb4[i] = A[4 * b + i] * xb4[i];
+    }
+  }
+  template <typename Acc>
+  __device__ void adj_finish(R wb, R s2, R ssx, Acc *tb) const {
+    tb[D_X] += (Acc)(ssx * sx);
+    tb[D_X + 1] += (Acc)mulz(wb, s2 - (R)D_X);
+  }
 };
 
 // x_t = x/2 + 25 x/(1+x^2) + 8 cos(1.2 t) + sx e;  y = x^2/20 + sy w;

@@ -162,21 +162,6 @@ __device__ __forceinline__ void filter_noise(int j0, uint32_t fid, uint32_t c3, 
   }
 }
 
-// The noise of one slot j of step t when the state dimension is a multiple of four (the same
-// numbers as filter_noise: blocks j * DX/4 .. j * DX/4 + DX/4 - 1).
-template <typename R, int DX>
-__device__ __forceinline__ void particle_noise(int j, uint32_t fid, uint32_t c3, uint32_t t,
-                                               uint64_t seed, R (&e)[DX]) {
-  static_assert(DX % 4 == 0, "one slot's noise fills whole Philox blocks");
-#pragma unroll
-  for (int b = 0; b < DX / 4; ++b) {
-    R z[4];
-    normals4<R>((uint32_t)(j * (DX / 4) + b), t, fid, c3, seed, z);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) e[4 * b + r] = z[r];
-  }
-}
-
 // Multinomial resampling uniforms of step t for offspring slots j0 .. j0 + PPL - 1: word i % 4
 // of block (i / 4, t).
 template <int PPL>
@@ -354,7 +339,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
     if (A.persistent) {
       if (tid == 0) sh_item = (int)atomicAdd(A.queue, 1u);
       __syncthreads();
-      idx = sh_item;
+      idx = __builtin_amdgcn_readfirstlane(sh_item);  // uniform: item-derived values stay scalar
     } else {
       if (round > 0) break;
       idx = blockIdx.x;
@@ -438,7 +423,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
         R *cks = ck + (size_t)ck_idx * (DX + 1) * LD;
 #pragma unroll
         for (int q = 0; q < DX; ++q) store_comp<PPL>(cks + q * LD + j0, x, q);
-        if (!lw_uniform) {
+        if (!lw_uniform && !(EVERY && kWide)) {
           if (lazy_lw) {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) sh_lw[j0 + p] = lW[p];
@@ -454,14 +439,29 @@ void pf_fwd_adj_kernel(PFArgs A) {
       const R *yv = sh_y + (size_t)(t - 1) * DY;
       R mloc = (R)kNegInf;  // a maximum is exact in R; it widens to FP64 unchanged
       if constexpr (kWide) {
+        // one particle and four components (one Philox block of its noise) at a time
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          R ep[DX];
-          particle_noise<R, DX>(j0 + p, fid, c3s, (uint32_t)t, seed, ep);
-          if (nz)
+          R s2 = (R)0;
 #pragma unroll
-            for (int q = 0; q < DX; ++q) nz[((size_t)t * DX + q) * LD + j0 + p] = ep[q];
-          R v = lW[p] + mdl.advance(x[p], ep, yv);  // lW now holds the unnormalised lw
+          for (int b = 0; b < DX / 4; ++b) {
+            R e4[4], x4[4];
+            // the block's counter is recomputed at every step rather than kept live across the
+            // loop (with its first Philox products) for all of a lane's blocks
+            uint32_t cb = (uint32_t)((j0 + p) * (DX / 4) + b);
+            asm volatile("" : "+v"(cb));
+            normals4<R>(cb, (uint32_t)t, fid, c3s, seed, e4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (nz) nz[((size_t)t * DX + 4 * b + i) * LD + j0 + p] = e4[i];
+              x4[i] = x[p][4 * b + i];
+            }
+            mdl.step_block(b, x4, e4);
+            mdl.resid_block(b, yv, x4, s2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[p][4 * b + i] = x4[i];
+          }
+          R v = lW[p] + mdl.logg_of(s2);  // lW now holds the unnormalised lw
           if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
           lW[p] = v;
           mloc = fmax(mloc, v);
@@ -538,6 +538,17 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) lin[p] = sh_lw[j0 + p];
         store_run<PPL>(ck + (size_t)(t - 1) * (DX + 1) * LD + DX * LD + j0, lin);
+      }
+      if constexpr (EVERY && kWide) {
+        // wide states: the adjoint restarts its weight adjoint from the step's normalised
+        // weights W = exp(lw - max) / S, stored in the checkpoint's log-weight row where it will
+        // (a resampled step or T), instead of rebuilding them from the carried log-weights
+        if (res || t == T) {
+          R wn[PPL];
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) wn[p] = (R)((double)ew[p] / S);
+          store_run<PPL>(ck + (size_t)(t - 1) * (DX + 1) * LD + DX * LD + j0, wn);
+        }
       }
       if (tid == 0) {
         g_s[t - 1] = S;
@@ -771,48 +782,64 @@ void pf_fwd_adj_kernel(PFArgs A) {
       // its weight, and differentiates it.
       zero_staging();
       if constexpr (kWide) {
-        // one particle at a time: its state before the step (checkpoint) and noise are read,
-        // the step and its weight rebuilt, and the step differentiated
+        // one particle and four components at a time: the block's state before the step
+        // (checkpoint) and noise are read, the block's step rebuilt and differentiated.  The
+        // weight adjoint restarts from the normalised weights the forward stored.  The lane's
+        // parameter adjoint is summed in R over 16 steps at a time, then over the wave in FP64
+        // into its LDS row.
+        R tpl[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) tpl[k] = (R)0;
+        int since = 0;
         for (int t = T; t >= 1; --t) {
           const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
           win(t);
           const bool res = t < T && flag_of(t);
-          const bool need_w = t == T || res;
-          R cl[PPL];
-          int ca[PPL];
-          load_run<PPL>(cks + DX * LD + j0, cl);
+          if (t == T || res) load_run<PPL>(cks + DX * LD + j0, wb);
           if (res) {
+            int ca[PPL];
             load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, ca);
             scatter_to_parents(ca);
           }
           mdl.per_step(t);
           const R *yv = sh_y + (size_t)(t - 1) * DY;
-          const R st = st_of(t);  // max_t + log S_t
-          R tp[NP];
-#pragma unroll
-          for (int k = 0; k < NP; ++k) tp[k] = (R)0;
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
-            R xp[DX], ep[DX], xn[DX];
+            R s2 = (R)0, ssx = (R)0;
 #pragma unroll
-            for (int q = 0; q < DX; ++q) xp[q] = cks[q * LD + j0 + p];
-            if (nz) {
+            for (int b = 0; b < DX / 4; ++b) {
+              R xp4[4], e4[4], xn4[4], xb4[4];
 #pragma unroll
-              for (int q = 0; q < DX; ++q) ep[q] = nz[((size_t)t * DX + q) * LD + j0 + p];
-            } else {
-              particle_noise<R, DX>(j0 + p, fid, c3s, (uint32_t)t, seed, ep);
+              for (int i = 0; i < 4; ++i) xp4[i] = cks[(4 * b + i) * LD + j0 + p];
+              if (nz) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) e4[i] = nz[((size_t)t * DX + 4 * b + i) * LD + j0 + p];
+              } else {
+                uint32_t cb = (uint32_t)((j0 + p) * (DX / 4) + b);
+                asm volatile("" : "+v"(cb));  // as in the forward
+                normals4<R>(cb, (uint32_t)t, fid, c3s, seed, e4);
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                xn4[i] = xp4[i];
+                xb4[i] = xb[p][4 * b + i];
+              }
+              mdl.step_block(b, xn4, e4);
+              mdl.adj_block(b, yv, xp4, xn4, e4, wb[p], xb4, tpl, s2, ssx);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) xb[p][4 * b + i] = xb4[i];
             }
-#pragma unroll
-            for (int q = 0; q < DX; ++q) xn[q] = xp[q];
-            const R lam = mdl.advance(xn, ep, yv);
-            if (need_w) {  // the weight adjoint restarts: the normalised weight of the step
-              R v = cl[p] + lam;
-              if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
-              wb[p] = fexp(v - st);
-            }
-            mdl.advance_adj(yv, xp, xn, ep, wb[p], xb[p], tp);
+            mdl.adj_finish(wb[p], s2, ssx, tpl);
           }
-          add_step_adjoint(tp);
+          if (++since == 16 || t == 1) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+              const double sk = wave_sum((double)tpl[k]);
+              if (lane == 0) sh_tb[wid * NP + k] += sk;
+              tpl[k] = (R)0;
+            }
+            since = 0;
+          }
         }
       } else {
       R nx[PPL][DX], nl[PPL], ne[PPL][DX];
