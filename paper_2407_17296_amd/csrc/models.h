@@ -10,6 +10,11 @@
 // `setup` receives the parameters (FP64) and the model constants (FP64, only the SIR model has
 // any).  DX / DY / NP: state, observation and parameter dimensions.
 //
+// Every model's noise enters through an invertible map, x_t = m(x_{t-1}, y_t, theta) + C e_t, so
+// `noise_of` recovers a step's noise from the states before and after it (up to rounding), and
+// `weight_of` gives its log incremental weight from the same two states: a reverse sweep that
+// has both states needs neither the random stream nor a rebuilt step.
+//
 // R is the arithmetic type of propagation and weighting (double in the plain FP64 form, float
 // in the mixed form).  Parameters arrive in FP64 and are transformed once in FP64.  Gradient
 // contributions are added into accumulators `tb` indexed like theta (type Acc: the kernel
@@ -46,6 +51,11 @@ struct Bootstrap {
     m.step(x, e);
     return m.logg(y, x);
   }
+  // the log incremental weight of a step from the states before (xp) and after (xn) it
+  __device__ R weight_of(const R *y, const R *, const R *xn) const {
+    const Derived &m = *static_cast<const Derived *>(this);
+    return m.logg(y, xn);
+  }
   // xb: adjoint of the state after the step on entry, before it on return; wb: adjoint of
   // the step's log-weight; xp / xn: the state before / after the step
   template <typename Acc>
@@ -61,17 +71,21 @@ struct Bootstrap {
 template <typename R>
 struct ModelLG1D : Bootstrap<ModelLG1D<R>, R> {
   static constexpr int DX = 1, DY = 1, NP = 3;
-  R a, sx, c0, isy;  // c0 = -log(2 pi)/2 - log sy
+  R a, sx, c0, isy, isx;  // c0 = -log(2 pi)/2 - log sy
   __device__ void setup(const double *th, const double *) {
     a = (R)th[0];
     sx = (R)exp(th[1]);
     c0 = (R)(-kHalfLog2Pi - th[2]);
     isy = (R)exp(-th[2]);
+    isx = (R)exp(-th[1]);
   }
   __device__ void per_step(int) {}
   __device__ void init(const R *e0, R *x) const { x[0] = e0[0]; }
   __device__ void init_adj(const R *, const R *, double *) const {}
   __device__ void step(R *x, const R *e) const { x[0] = fmar(a, x[0], sx * e[0]); }
+  __device__ void noise_of(const R *xp, const R *xn, const R *, R *e) const {
+    e[0] = (xn[0] - a * xp[0]) * isx;
+  }
   // reverse of step: tb += F_theta^T xb;  xb <- F_x^T xb   (xp = state before the step)
   template <typename Acc>
   __device__ void step_adj(const R *xp, const R *e, R *xb, Acc *tb) const {
@@ -196,11 +210,12 @@ struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
 template <typename R>
 struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
   static constexpr int DX = 1, DY = 1, NP = 2;
-  R sx, c0, isy, drive;  // c0 = -log(2 pi)/2 - log sy
+  R sx, c0, isy, drive, isx;  // c0 = -log(2 pi)/2 - log sy
   __device__ void setup(const double *th, const double *) {
     sx = (R)exp(th[0]);
     c0 = (R)(-kHalfLog2Pi - th[1]);
     isy = (R)exp(-th[1]);
+    isx = (R)exp(-th[0]);
     drive = (R)0;
   }
   // the deterministic forcing of step t, evaluated once per step in FP64
@@ -210,6 +225,11 @@ struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
   __device__ void step(R *x, const R *e) const {
     const R v = x[0];
     x[0] = fmar((R)0.5, v, (R)25 * v * frcp(fmar(v, v, (R)1))) + fmar(sx, e[0], drive);
+  }
+  // per_step(t) sets the forcing first
+  __device__ void noise_of(const R *xp, const R *xn, const R *, R *e) const {
+    const R v = xp[0];
+    e[0] = (xn[0] - fmar((R)0.5, v, (R)25 * v * frcp(fmar(v, v, (R)1))) - drive) * isx;
   }
   template <typename Acc>
   __device__ void step_adj(const R *xp, const R *e, R *xb, Acc *tb) const {
@@ -235,13 +255,14 @@ struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
 template <typename R>
 struct ModelSV : Bootstrap<ModelSV<R>, R> {
   static constexpr int DX = 1, DY = 1, NP = 3;
-  R mu, phi, s, sd0, dsd0;  // dsd0 = d sd0 / d theta_1 = s sinh(theta_1)
+  R mu, phi, s, sd0, dsd0, is;  // dsd0 = d sd0 / d theta_1 = s sinh(theta_1), is = 1 / s
   __device__ void setup(const double *th, const double *) {
     mu = (R)th[0];
     phi = (R)tanh(th[1]);
     s = (R)exp(th[2]);
     sd0 = (R)(exp(th[2]) * cosh(th[1]));
     dsd0 = (R)(exp(th[2]) * sinh(th[1]));
+    is = (R)exp(-th[2]);
   }
   __device__ void per_step(int) {}
   __device__ void init(const R *e0, R *x) const { x[0] = fmar(sd0, e0[0], mu); }
@@ -252,6 +273,9 @@ struct ModelSV : Bootstrap<ModelSV<R>, R> {
   }
   __device__ void step(R *x, const R *e) const {
     x[0] = fmar(phi, x[0] - mu, fmar(s, e[0], mu));
+  }
+  __device__ void noise_of(const R *xp, const R *xn, const R *, R *e) const {
+    e[0] = (xn[0] - fmar(phi, xp[0] - mu, mu)) * is;
   }
   template <typename Acc>
   __device__ void step_adj(const R *xp, const R *e, R *xb, Acc *tb) const {
@@ -278,7 +302,7 @@ struct ModelLG1DOpt {
   static constexpr int DX = 1, DY = 1, NP = 3;
   // kx = dm/dx = rho^2 a / sx^2, ky = rho^2 / sy^2, rx = rho^2 / sx^2, c0 = -log(2 pi)/2 -
   // log(s2)/2 and is2 = 1/s2 with s2 = sx^2 + sy^2, fx / fy = sx^2 / s2, sy^2 / s2
-  R a, kx, ky, rx, rho, c0, is2, fx, fy;
+  R a, kx, ky, rx, rho, c0, is2, fx, fy, irho;
   __device__ void setup(const double *th, const double *) {
     const double vx = exp(2.0 * th[1]), vy = exp(2.0 * th[2]);
     const double rho2 = 1.0 / (1.0 / vx + 1.0 / vy), s2 = vx + vy;
@@ -287,6 +311,7 @@ struct ModelLG1DOpt {
     ky = (R)(rho2 / vy);
     rx = (R)(rho2 / vx);
     rho = (R)sqrt(rho2);
+    irho = (R)(1.0 / sqrt(rho2));
     c0 = (R)(-kHalfLog2Pi - 0.5 * log(s2));
     is2 = (R)(1.0 / s2);
     fx = (R)(vx / s2);
@@ -299,6 +324,14 @@ struct ModelLG1DOpt {
     const R xo = x[0], r = fmar(-a, xo, y[0]);
     x[0] = fmar(ky, y[0], fmar(kx, xo, rho * e[0]));
     return fmar((R)-0.5 * r * is2, r, c0);
+  }
+  // the predictive weight depends on the state before the step only
+  __device__ R weight_of(const R *y, const R *xp, const R *) const {
+    const R r = fmar(-a, xp[0], y[0]);
+    return fmar((R)-0.5 * r * is2, r, c0);
+  }
+  __device__ void noise_of(const R *xp, const R *xn, const R *y, R *e) const {
+    e[0] = (xn[0] - fmar(ky, y[0], kx * xp[0])) * irho;
   }
   template <typename Acc>
   __device__ void advance_adj(const R *y, const R *xp, const R *xn, const R *e, R wb, R *xb,
@@ -351,6 +384,11 @@ struct ModelSIR : Bootstrap<ModelSIR<R>, R> {
     const R inf = bn * I * S;  // new infections
     x[0] = fmar(se, e[0], S - inf);
     x[1] = fmar(se, e[1] - e[0], fmar(-gam, I, I) + inf);
+  }
+  // the noise does not depend on theta, so the adjoint never reads it
+  __device__ void noise_of(const R *, const R *, const R *, R *e) const {
+    e[0] = (R)0;
+    e[1] = (R)0;
   }
   // inf enters S with -1 and I with +1, so its adjoint is xb_I - xb_S
   template <typename Acc>

@@ -301,6 +301,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
   // step, so that a lane holds only its particles' states and adjoints across steps, and sum the
   // parameter adjoint per wave into LDS instead of keeping NP FP64 accumulators per lane.
   constexpr bool kWide = DX % 4 == 0;
+  // With a checkpoint at every step (states of one or two components), row t of the checkpoints
+  // holds the state after step t, before its resampling (row 0: x_0): the reverse sweep then has
+  // the states on both sides of each step, the one before gathered from row t - 1 through the
+  // stored ancestors, and recovers the step's noise from them instead of drawing it again.
+  constexpr bool kPost = EVERY && !kWide;
   // the multinomial prefix (MP doubles) or the systematic first-offspring markers with a dummy
   // per lane (MP + 64 ints): a launch uses one resampler, so the two share their LDS
   __shared__ double sh_pm[MP];
@@ -402,6 +407,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
         lW[p] = lWeqR;
       }
     }
+    if constexpr (kPost) {
+#pragma unroll
+      for (int q = 0; q < DX; ++q) store_comp<PPL>(ck + q * LD + j0, x, q);
+    }
     bool dead = false;
     int nres = 0;
     int ck_left = 0, ck_idx = 0;
@@ -421,8 +430,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
       const bool lwu_in = lw_uniform;
       if (ck_left == 0) {
         R *cks = ck + (size_t)ck_idx * (DX + 1) * LD;
+        if constexpr (!kPost) {
 #pragma unroll
-        for (int q = 0; q < DX; ++q) store_comp<PPL>(cks + q * LD + j0, x, q);
+          for (int q = 0; q < DX; ++q) store_comp<PPL>(cks + q * LD + j0, x, q);
+        }
         if (!lw_uniform && !(EVERY && kWide)) {
           if (lazy_lw) {
 #pragma unroll
@@ -476,6 +487,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
           if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
           lW[p] = v;
           mloc = fmax(mloc, v);
+        }
+        if constexpr (kPost) {
+          R *ckt = ck + (size_t)t * (DX + 1) * LD;
+#pragma unroll
+          for (int q = 0; q < DX; ++q) store_comp<PPL>(ckt + q * LD + j0, x, q);
         }
       }
       // log-sum-exp, exchange 1: the maximum (a single wave holds it already)
@@ -842,67 +858,100 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
         }
       } else {
-      R nx[PPL][DX], nl[PPL], ne[PPL][DX];
-      int na[PPL];
-      // reads the flags of steps t and t - 1 from the window of step t or t + 1
-      auto load_trace = [&](int t) {
-        const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
-        const bool lres = t < T && flag_of(t);
+        // Row t holds the state after step t before its resampling.  Step t is taken from the
+        // state after it (xn, row t) and the state before it: the state after step t - 1 (row
+        // t - 1), gathered through the ancestors of that step's resampling.  Row t - 2 and the
+        // ancestors of step t - 1 are loaded while step t is processed.
+        auto load_row = [&](int r, R (&v)[PPL][DX]) {
+          const R *ckr = ck + (size_t)r * (DX + 1) * LD;
 #pragma unroll
-        for (int q = 0; q < DX; ++q) {
-          load_comp<PPL>(cks + q * LD + j0, nx, q);
-          if (nz) load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ne, q);
+          for (int q = 0; q < DX; ++q) load_comp<PPL>(ckr + q * LD + j0, v, q);
+        };
+        R xn[PPL][DX], xq[PPL][DX];  // the states after steps t and t - 1
+        int ca[PPL];                 // ancestors of the resampling after step t
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) ca[p] = 0;
+        if (T > 0) {
+          load_row(T, xn);
+          load_row(T - 1, xq);
         }
-        // the carry into step t was stored only where the step's weights are rebuilt (a
-        // resampled step or T) and it was not the uniform -log M
-        if ((t == T || lres) && t > 1 && !flag_of(t - 1))
-          load_run<PPL>(cks + DX * LD + j0, nl);
-        else
+        for (int t = T; t >= 1; --t) {
+          win(t);
+          const bool res_t = t < T && flag_of(t);
+          const bool res_p = t > 1 && flag_of(t - 1);  // resampled after step t - 1
+          const bool need_w = t == T || res_t;
+          // the carry into step t, stored where the weights are rebuilt and not uniform
+          R cl[PPL];
+          if (need_w && t > 1 && !res_p)
+            load_run<PPL>(ck + (size_t)(t - 1) * (DX + 1) * LD + DX * LD + j0, cl);
+          else
 #pragma unroll
-          for (int p = 0; p < PPL; ++p) nl[p] = lWeqR;
-        if (lres)
-          load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, na);
-        else
+            for (int p = 0; p < PPL; ++p) cl[p] = lWeqR;
+          int pa[PPL];
+          if (res_p)
+            load_run<PPL>(anc + (size_t)(t - 2) * LD + j0, pa);
+          else
 #pragma unroll
-          for (int p = 0; p < PPL; ++p) na[p] = 0;
-      };
-      if (T > 0) win(T);
-      if (kPrefetch && T > 0) load_trace(T);
-      for (int t = T; t >= 1; --t) {
-        R cx[PPL][DX], ce[PPL][DX], cl[PPL], cw[PPL];
-        int ca[PPL];
-        win(t);
-        if (!kPrefetch) load_trace(t);
+            for (int p = 0; p < PPL; ++p) pa[p] = 0;
+          R xq2[PPL][DX];  // the state after step t - 2, for the next step
+          if (t >= 2) load_row(t - 2, xq2);
+          // the state before step t
+          R xp[PPL][DX];
+          if (res_p) {
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
+            for (int q = 0; q < DX; ++q) {
+              __syncthreads();  // earlier readers of the staging are done
 #pragma unroll
-          for (int q = 0; q < DX; ++q) {
-            cx[p][q] = nx[p][q];
-            ce[p][q] = ne[p][q];
+              for (int p = 0; p < PPL; ++p) sh_lw[j0 + p] = xq[p][q];
+              __syncthreads();
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) xp[p][q] = sh_lw[pa[p]];
+            }
+          } else {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p)
+#pragma unroll
+              for (int q = 0; q < DX; ++q) xp[p][q] = xq[p][q];
           }
-          cl[p] = nl[p];
-          ca[p] = na[p];
-        }
-        if (kPrefetch && t > 1) load_trace(t - 1);
-        if (!nz) filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, ce);
-        mdl.per_step(t);
-        const R *yv = sh_y + (size_t)(t - 1) * DY;
-        const bool need_w = t == T || flag_of(t);
-        const R st = st_of(t);  // max_t + log S_t
+          mdl.per_step(t);
+          const R *yv = sh_y + (size_t)(t - 1) * DY;
+          // the step's noise: read back where the forward stored it, else recovered
+          R ce[PPL][DX];
+          if (nz) {
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          cw[p] = (R)0;
+            for (int q = 0; q < DX; ++q)
+              load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ce, q);
+          } else {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) mdl.noise_of(xp[p], xn[p], yv, ce[p]);
+          }
+          // the weight adjoint restarts from the step's normalised weights
           if (need_w) {
-            R xn[DX];
+            const R st = st_of(t);  // max_t + log S_t
 #pragma unroll
-            for (int q = 0; q < DX; ++q) xn[q] = cx[p][q];
-            R v = cl[p] + mdl.advance(xn, ce[p], yv);
-            if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
-            cw[p] = fexp(v - st);
+            for (int p = 0; p < PPL; ++p) {
+              R v = cl[p] + mdl.weight_of(yv, xp[p], xn[p]);
+              if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
+              wb[p] = fexp(v - st);
+            }
+          }
+          if (res_t) scatter_to_parents(ca);
+          R tp[NP];
+#pragma unroll
+          for (int k = 0; k < NP; ++k) tp[k] = (R)0;
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) mdl.advance_adj(yv, xp[p], xn[p], ce[p], wb[p], xb[p], tp);
+          add_step_adjoint(tp);
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            ca[p] = pa[p];
+#pragma unroll
+            for (int q = 0; q < DX; ++q) {
+              xn[p][q] = xq[p][q];
+              xq[p][q] = xq2[p][q];
+            }
           }
         }
-        reverse_step(t, cx, ce, cw, ca);
-      }
       }
     } else {
       // segment rows of one step: x before the step (DX rows), the noise when it is not

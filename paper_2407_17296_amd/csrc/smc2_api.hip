@@ -270,7 +270,9 @@ smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, in
   const int Tc = std::max(T_max, 1);
   L.c = o->ckpt_interval > 0 ? o->ckpt_interval : (int)std::ceil(std::sqrt((double)Tc));
   L.c = std::max(1, std::min(L.c, Tc));
-  L.nseg = (Tc + L.c - 1) / L.c;
+  // checkpoint rows: one per segment, plus one (with a checkpoint at every step the rows hold
+  // the states after steps 0 .. T)
+  L.nseg = (Tc + L.c - 1) / L.c + 1;
   const long items = (long)S * N;
   L.slots = (int)(o->persistent ? std::min<long>(items, grid_slots) : items);
   const size_t rs = o->precision == SMC2_FP64 ? 8 : 4;
