@@ -132,7 +132,10 @@ smc2_status smc2_ctx_create(smc2_ctx **out, int device);
  * layout).  Must precede graph capture; calls made with larger sizes than reserved fail with
  * SMC2_E_INVALID_ARG.  scratch_budget_bytes = 0 means no limit beyond device memory; a larger
  * need returns SMC2_E_OUT_OF_MEMORY and allocates nothing.  T_len (host [S]) gives each series'
- * length, used to order work longest first. */
+ * length, used to order work longest first.  SMC2_E_UNSUPPORTED when M is above the largest
+ * built tile, when the series do not fit the kernel's LDS staging, or when one filter's
+ * checkpoints or stored noise would take 4 GiB or more (they are addressed with 32-bit
+ * offsets). */
 smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_pf_opts *opts,
                              int32_t S, int32_t N, int32_t M, const int32_t *T_len,
                              int32_t T_max, size_t scratch_budget_bytes);

@@ -216,6 +216,15 @@ __device__ __forceinline__ void load_comp(const T *src, T (&v)[N][DX], int q) {
   for (int i = 0; i < N; ++i) v[i][q] = r[i];
 }
 
+// The wave's index in the workgroup as a scalar that the compiler cannot see through: the
+// per-wave conditions formed from it inside a loop (w == wid, w < wid for every wave w) are then
+// formed where used instead of being hoisted out of the loop and held in registers.
+__device__ __forceinline__ int wave_id_opaque() {
+  int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  asm volatile("" : "+s"(w));
+  return w;
+}
+
 // ---- wave and workgroup reductions ------------------------------------------------------------
 // Cross-lane moves use the data-parallel (DPP) modifiers of GFX9 VALU instructions instead of
 // LDS permutes: quad swaps and row mirrors for butterflies inside each row of 16 lanes, row
@@ -368,6 +377,27 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
   }
 }
 
+// Sum of D values per thread over the workgroup (D <= 64), delivered to thread p for value p
+// (0 in the other threads): the waves' sums are added in wave order, as in block_sum_vec.  A
+// thread adds one column only, so the workgroup does not hold every total in every thread.
+template <int WAVES, int D>
+__device__ __forceinline__ double block_sum_to_thread(double *v, double *red) {
+#pragma unroll
+  for (int p = 0; p < D; ++p) v[p] = wave_sum(v[p]);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int p = 0; p < D; ++p) red[wid * D + p] = v[p];
+  __syncthreads();
+  double r = 0.0;
+  if (tid < D) {
+    r = red[tid];
+    for (int w = 1; w < WAVES; ++w) r += red[w * D + tid];
+  }
+  return r;
+}
+
 // Sum of D values per thread over the workgroup (D <= 32); result valid in every thread.
 template <int WAVES, int D>
 __device__ __forceinline__ void block_sum_vec(double *v, double *red) {
@@ -393,7 +423,7 @@ __device__ __forceinline__ void block_sum_vec(double *v, double *red) {
 // exclusive prefix and sets `total` (identical in all threads).
 template <int WAVES>
 __device__ __forceinline__ double block_exclusive_scan(double v, double *wsum, double &total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = wave_id_opaque();
   const double inc = wave_inclusive_sum(v);
   const double exc = dpp_f64<kDppWaveShr1>(0.0, inc);
   const double wtot = readlane_f64(inc, 63);
@@ -419,7 +449,7 @@ __device__ __forceinline__ double block_exclusive_scan(double v, double *wsum, d
 // thread 0.
 template <int WAVES>
 __device__ __forceinline__ int block_exclusive_max_scan(int v, int *wmax) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = wave_id_opaque();
   const int inc = wave_inclusive_max(v);
   int exc = dpp_i32<kDppWaveShr1>(-1, inc);
   if constexpr (WAVES > 1) {

@@ -46,6 +46,9 @@ __device__ __forceinline__ double fmar(double a, double b, double c) {
 // (logg / logg_adj): advance = step then log g at the new state.
 template <class Derived, typename R>
 struct Bootstrap {
+  // values of theta the model keeps in LDS (one copy per workgroup) instead of registers
+  static constexpr int kShared = 0;
+  __device__ void bind_shared(R *) {}
   __device__ R advance(R *x, const R *e, const R *y) const {
     const Derived &m = *static_cast<const Derived *>(this);
     m.step(x, e);
@@ -111,10 +114,17 @@ struct ModelLG1D : Bootstrap<ModelLG1D<R>, R> {
 template <typename R, int D_X>
 struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
   static constexpr int DX = D_X, DY = D_X, NP = D_X + 2;
-  R A[D_X], sx, c0, isy;  // c0 = d (-log(2 pi)/2 - log sy)
+  // the diagonal A is the same for every particle of the workgroup: it lives in LDS (bound
+  // before setup), where a block of four reads it with one broadcast load
+  static constexpr int kShared = D_X;
+  R *A;
+  R sx, c0, isy;  // c0 = d (-log(2 pi)/2 - log sy)
+  __device__ void bind_shared(R *sh) { A = sh; }
+  // one thread writes A; the caller makes the writes visible before the first step
   __device__ void setup(const double *th, const double *) {
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < D_X; ++q) A[q] = (R)th[q];
+      for (int q = 0; q < D_X; ++q) A[q] = (R)th[q];
     sx = (R)exp(th[D_X]);
     c0 = (R)((double)D_X * (-kHalfLog2Pi - th[D_X + 1]));
     isy = (R)exp(-th[D_X + 1]);
@@ -166,6 +176,11 @@ struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
   // them only through its sum of squared residuals.  Taking the blocks in order reproduces the
   // sums of step / logg / logg_adj / step_adj bit for bit.
   static constexpr bool kBlocks = true;
+  // the start of a block from its noise
+  __device__ void init_block(int, const R (&e4)[4], R (&x4)[4]) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x4[i] = e4[i];
+  }
   __device__ void step_block(int b, R (&x4)[4], const R (&e4)[4]) const {
 #pragma unroll
     for (int i = 0; i < 4; ++i) x4[i] = fmar(A[4 * b + i], x4[i], sx * e4[i]);
@@ -180,11 +195,13 @@ struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
   }
   __device__ R logg_of(R s2) const { return fmar((R)-0.5, s2, c0); }
   // the transposed step of a block: xb4 holds the block's state adjoint after the step on entry
-  // and before it on return; tb receives the adjoints of A_{4b..4b+3}; s2 and ssx carry the sums
-  // whose adjoints adj_finish adds once all blocks are done
+  // and before it on return; tb4 receives the adjoints of the block's parameters A_{4b..4b+3}
+  // (parameter 4b + i of theta); s2 and ssx carry the sums whose adjoints adj_finish adds once
+  // all blocks are done
   template <typename Acc>
   __device__ void adj_block(int b, const R *y, const R (&xp4)[4], const R (&xn4)[4],
-                            const R (&e4)[4], R wb, R (&xb4)[4], Acc *tb, R &s2, R &ssx) const {
+                            const R (&e4)[4], R wb, R (&xb4)[4], Acc (&tb4)[4], R &s2,
+                            R &ssx) const {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const R r = (y[4 * b + i] - xn4[i]) * isy;
@@ -193,7 +210,7 @@ struct ModelLGDiag : Bootstrap<ModelLGDiag<R, D_X>, R> {
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      tb[4 * b + i] += (Acc)mulz(xb4[i], xp4[i]);
+      tb4[i] += (Acc)mulz(xb4[i], xp4[i]);
       ssx += mulz(xb4[i], e4[i]);
       xb4[i] = A[4 * b + i] * xb4[i];
     }
@@ -300,6 +317,8 @@ struct ModelSV : Bootstrap<ModelSV<R>, R> {
 template <typename R>
 struct ModelLG1DOpt {
   static constexpr int DX = 1, DY = 1, NP = 3;
+  static constexpr int kShared = 0;  // as for the bootstrap models: nothing in LDS
+  __device__ void bind_shared(R *) {}
   // kx = dm/dx = rho^2 a / sx^2, ky = rho^2 / sy^2, rx = rho^2 / sx^2, c0 = -log(2 pi)/2 -
   // log(s2)/2 and is2 = 1/s2 with s2 = sx^2 + sy^2, fx / fy = sx^2 / s2, sy^2 / s2
   R a, kx, ky, rx, rho, c0, is2, fx, fy, irho;

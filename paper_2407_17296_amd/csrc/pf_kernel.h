@@ -283,6 +283,14 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
   for (int p = 0; p < PPL; ++p) a[p] = min(max(a[p], before), M - 1);
 }
 
+// An element of a region that starts at a uniform base, addressed by a 32-bit byte offset (the
+// region is below 4 GiB): the base stays in scalar registers, and an access needs one 32-bit
+// offset register instead of a 64-bit address per row.
+template <typename T>
+__device__ __forceinline__ T &at_off(T *base, uint32_t byte_off) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+
 // EVERY: a checkpoint at every step (the reverse sweep rebuilds each step from the state before
 // it); otherwise checkpoints every A.ckpt steps and segments recomputed forward.  The two are
 // separate instantiations so that neither carries the other's registers.
@@ -318,6 +326,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
   __shared__ double sh_ex[2][3 * WAVES];  // per-wave max and (sum, sum of squares), ping-pong
   __shared__ double sh_vec[WAVES * NP];
   __shared__ double sh_tb[kWide ? WAVES * NP : 1];  // per-wave parameter adjoint (wide states)
+  // wide states with a checkpoint at every step: each lane's running sums of the blocks'
+  // parameter adjoints (four per block) wait in LDS between the steps, as [block][lane][4],
+  // where they fit in 64 KiB
+  constexpr bool kTaLds = kWide && EVERY && DX * NT * sizeof(R) <= 65536;
+  __shared__ __align__(16) R sh_ta[kTaLds ? DX * NT : 4];
+  __shared__ __align__(16) R sh_model[Model::kShared > 0 ? Model::kShared : 1];
   __shared__ int sh_imax[WAVES];
   __shared__ int sh_item;
   extern __shared__ double sh_dyn[];
@@ -325,7 +339,6 @@ void pf_fwd_adj_kernel(PFArgs A) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  const int j0 = tid * PPL;
   const int M = A.M;
   const double Md = (double)M;
   const uint32_t k = *A.iteration;
@@ -339,6 +352,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
   const size_t LD = (size_t)A.ld;
 
   for (int round = 0;; ++round) {
+    // the lane's first slot, opaque once per item: what is formed from it (noise counters and
+    // their first Philox products, addresses) is formed within the item, not held across items
+    int j0 = tid * PPL;
+    asm volatile("" : "+v"(j0));
     int idx;
     __syncthreads();  // the previous item is done with every shared array
     if (A.persistent) {
@@ -370,6 +387,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       continue;
     }
     Model mdl;
+    mdl.bind_shared(sh_model);
     mdl.setup(thv, A.mconst);
     {
       const double *ys = A.y + (size_t)s * A.T_max * DY;
@@ -397,15 +415,28 @@ void pf_fwd_adj_kernel(PFArgs A) {
 
     // ---- forward ------------------------------------------------------------------------------
     R x[PPL][DX], lW[PPL];
-    {
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
+    if constexpr (kWide) {  // block by block, as the steps
+#pragma unroll
+      for (int b = 0; b < DX / 4; ++b)
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          R e4[4], x4[4];
+          normals4<R>((uint32_t)((j0 + p) * (DX / 4) + b), 0u, fid, c3i, seed, e4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (nz) nz[(size_t)(4 * b + i) * LD + j0 + p] = e4[i];
+          mdl.init_block(b, e4, x4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[p][4 * b + i] = x4[i];
+        }
+    } else {
       R e[PPL][DX];
       filter_noise<R, DX, PPL>(j0, fid, c3i, 0u, seed, e);
       if (nz) store_noise(0, e);
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        mdl.init(e[p], x[p]);
-        lW[p] = lWeqR;
-      }
+      for (int p = 0; p < PPL; ++p) mdl.init(e[p], x[p]);
     }
     if constexpr (kPost) {
 #pragma unroll
@@ -450,29 +481,51 @@ void pf_fwd_adj_kernel(PFArgs A) {
       const R *yv = sh_y + (size_t)(t - 1) * DY;
       R mloc = (R)kNegInf;  // a maximum is exact in R; it widens to FP64 unchanged
       if constexpr (kWide) {
-        // one particle and four components (one Philox block of its noise) at a time
+        // four components (one Philox block of the noise) of every particle of the lane at a
+        // time: the lane's particles are adjacent, so a block's loads and stores serve them all
+        R s2[PPL];
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          R s2 = (R)0;
+        for (int p = 0; p < PPL; ++p) s2[p] = (R)0;
+        // with and without the noise stores as two loops: a store under a per-block branch would
+        // split the blocks, and the steps would then wait below all of them with every noise
+        auto blocks = [&](auto keep) {
+          // the blocks' counters are recomputed at every step from an opaque copy of j0 rather
+          // than kept live across the loop (with their first Philox products)
+          int jb = j0;
+          asm volatile("" : "+v"(jb));
+          // the row pitch in bytes, opaque so that the rows' offsets are formed where used
+          uint32_t pitch = (uint32_t)(LD * sizeof(R));
+          asm volatile("" : "+s"(pitch));
+          const uint32_t lo = (uint32_t)jb * (uint32_t)sizeof(R);
 #pragma unroll
           for (int b = 0; b < DX / 4; ++b) {
-            R e4[4], x4[4];
-            // the block's counter is recomputed at every step rather than kept live across the
-            // loop (with its first Philox products) for all of a lane's blocks
-            uint32_t cb = (uint32_t)((j0 + p) * (DX / 4) + b);
-            asm volatile("" : "+v"(cb));
-            normals4<R>(cb, (uint32_t)t, fid, c3s, seed, e4);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (nz) nz[((size_t)t * DX + 4 * b + i) * LD + j0 + p] = e4[i];
-              x4[i] = x[p][4 * b + i];
+            for (int p = 0; p < PPL; ++p) {
+              R e4[4], x4[4];
+              const uint32_t cb = (uint32_t)((jb + p) * (DX / 4) + b);
+              normals4<R>(cb, (uint32_t)t, fid, c3s, seed, e4);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if constexpr (decltype(keep)::value)
+                  at_off(nz, ((uint32_t)t * DX + 4 * b + i) * pitch + lo +
+                                 (uint32_t)(p * sizeof(R))) = e4[i];
+                x4[i] = x[p][4 * b + i];
+              }
+              mdl.step_block(b, x4, e4);
+              mdl.resid_block(b, yv, x4, s2[p]);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) x[p][4 * b + i] = x4[i];
+              if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
             }
-            mdl.step_block(b, x4, e4);
-            mdl.resid_block(b, yv, x4, s2);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) x[p][4 * b + i] = x4[i];
           }
-          R v = lW[p] + mdl.logg_of(s2);  // lW now holds the unnormalised lw
+        };
+        if (nz)
+          blocks(std::true_type{});
+        else
+          blocks(std::false_type{});
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          R v = lW[p] + mdl.logg_of(s2[p]);  // lW now holds the unnormalised lw
           if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
           lW[p] = v;
           mloc = fmax(mloc, v);
@@ -540,9 +593,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
         }
         __syncthreads();
+        const int widu = wave_id_opaque();
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) {
-          if (w == wid) off = S;
+          if (w == widu) off = S;
           S = S + ex[WAVES + 2 * w];
           Q = Q + ex[WAVES + 2 * w + 1];
         }
@@ -806,6 +860,15 @@ void pf_fwd_adj_kernel(PFArgs A) {
         R tpl[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) tpl[k] = (R)0;
+        auto ta_row = [&](int b) -> R(&)[4] {
+          return *reinterpret_cast<R(*)[4]>(&sh_ta[((size_t)b * NT + tid) * 4]);
+        };
+        if constexpr (kTaLds) {
+#pragma unroll
+          for (int b = 0; b < DX / 4; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ta_row(b)[i] = (R)0;
+        }
         int since = 0;
         for (int t = T; t >= 1; --t) {
           const R *cks = ck + (size_t)(t - 1) * (DX + 1) * LD;
@@ -819,38 +882,73 @@ void pf_fwd_adj_kernel(PFArgs A) {
           }
           mdl.per_step(t);
           const R *yv = sh_y + (size_t)(t - 1) * DY;
+          R s2[PPL], ssx[PPL];
 #pragma unroll
-          for (int p = 0; p < PPL; ++p) {
-            R s2 = (R)0, ssx = (R)0;
+          for (int p = 0; p < PPL; ++p) s2[p] = ssx[p] = (R)0;
+          auto blocks = [&](auto stored) {  // noise read back or drawn again (as in the forward)
+            int jb = j0;
+            asm volatile("" : "+v"(jb));
+            uint32_t pitch = (uint32_t)(LD * sizeof(R));  // as in the forward
+            asm volatile("" : "+s"(pitch));
+            const uint32_t lo = (uint32_t)jb * (uint32_t)sizeof(R);
 #pragma unroll
             for (int b = 0; b < DX / 4; ++b) {
-              R xp4[4], e4[4], xn4[4], xb4[4];
+              R ta[4];
 #pragma unroll
-              for (int i = 0; i < 4; ++i) xp4[i] = cks[(4 * b + i) * LD + j0 + p];
-              if (nz) {
+              for (int i = 0; i < 4; ++i) ta[i] = kTaLds ? ta_row(b)[i] : tpl[4 * b + i];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) e4[i] = nz[((size_t)t * DX + 4 * b + i) * LD + j0 + p];
-              } else {
-                uint32_t cb = (uint32_t)((j0 + p) * (DX / 4) + b);
-                asm volatile("" : "+v"(cb));  // as in the forward
-                normals4<R>(cb, (uint32_t)t, fid, c3s, seed, e4);
+              for (int p = 0; p < PPL; ++p) {
+                R xp4[4], e4[4], xn4[4], xb4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  xp4[i] = at_off(ck, ((uint32_t)(t - 1) * (DX + 1) + 4 * b + i) * pitch + lo +
+                                          (uint32_t)(p * sizeof(R)));
+                if constexpr (decltype(stored)::value) {
+#pragma unroll
+                  for (int i = 0; i < 4; ++i)
+                    e4[i] = at_off(nz, ((uint32_t)t * DX + 4 * b + i) * pitch + lo +
+                                           (uint32_t)(p * sizeof(R)));
+                } else {
+                  const uint32_t cb = (uint32_t)((jb + p) * (DX / 4) + b);
+                  normals4<R>(cb, (uint32_t)t, fid, c3s, seed, e4);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  xn4[i] = xp4[i];
+                  xb4[i] = xb[p][4 * b + i];
+                }
+                mdl.step_block(b, xn4, e4);
+                mdl.adj_block(b, yv, xp4, xn4, e4, wb[p], xb4, ta, s2[p], ssx[p]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xb[p][4 * b + i] = xb4[i];
+                if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
               }
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                xn4[i] = xp4[i];
-                xb4[i] = xb[p][4 * b + i];
+                if constexpr (kTaLds)
+                  ta_row(b)[i] = ta[i];
+                else
+                  tpl[4 * b + i] = ta[i];
               }
-              mdl.step_block(b, xn4, e4);
-              mdl.adj_block(b, yv, xp4, xn4, e4, wb[p], xb4, tpl, s2, ssx);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) xb[p][4 * b + i] = xb4[i];
             }
-            mdl.adj_finish(wb[p], s2, ssx, tpl);
-          }
+          };
+          if (nz)
+            blocks(std::true_type{});
+          else
+            blocks(std::false_type{});
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) mdl.adj_finish(wb[p], s2[p], ssx[p], tpl);
           if (++since == 16 || t == 1) {
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-              const double sk = wave_sum((double)tpl[k]);
+              R v = tpl[k];
+              if constexpr (kTaLds) {
+                if (k < DX) {
+                  v = ta_row(k / 4)[k % 4];
+                  ta_row(k / 4)[k % 4] = (R)0;
+                }
+              }
+              const double sk = wave_sum((double)v);
               if (lane == 0) sh_tb[wid * NP + k] += sk;
               tpl[k] = (R)0;
             }
@@ -1084,17 +1182,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
       for (int p = 0; p < PPL; ++p) mdl.init_adj(e[p], xb[p], tb);
     }
-    block_sum_vec<WAVES, NP>(tb, sh_vec);  // its barriers also publish sh_tb
-    if constexpr (kWide) {
-#pragma unroll
-      for (int k = 0; k < NP; ++k)
-        for (int w = 0; w < WAVES; ++w) tb[k] += sh_tb[w * NP + k];
-    }
+    // thread k receives parameter k's total (the barriers also publish sh_tb)
+    double v = block_sum_to_thread<WAVES, NP>(tb, sh_vec);
     if (tid < NP) {
-      double v = tb[0];
-#pragma unroll
-      for (int p = 1; p < NP; ++p)
-        if (tid == p) v = tb[p];
+      if constexpr (kWide)  // and adds the per-wave sums of the wide sweep
+        for (int w = 0; w < WAVES; ++w) v += sh_tb[w * NP + tid];
       gout[tid] = v;
     }
   }

@@ -14,7 +14,7 @@ struct PFKernel {
   void (*launch)(const PFArgs &, int grid, hipStream_t);
   int (*occupancy)(int lds_T, int every);
   size_t (*dyn_lds)(int lds_T);      // dynamic shared memory per workgroup
-  size_t static_lds;                 // static shared memory per workgroup (upper bound)
+  size_t (*static_lds)();            // static shared memory per workgroup (both sweeps' maximum)
 };
 
 // Launch shapes (tile index -> waves per workgroup, particles per lane).  Index 0 is "tuned".
@@ -55,13 +55,28 @@ int occupancy_pf(int lds_T, int every) {
   return n;
 }
 
+// as the compiler laid it out; the kernels' own arrays otherwise take at most 64 KiB plus the
+// per-particle staging
+template <typename R, class Model, int W, int P>
+size_t static_lds_pf() {
+  size_t n = 0;
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(
+                                    &pf_fwd_adj_kernel<R, Model, W, P, true>)) == hipSuccess)
+    n = std::max(n, fa.sharedSizeBytes);
+  else
+    n = 65536 + (size_t)W * 64 * P * (sizeof(double) + 3 * sizeof(R)) + 4096;
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(
+                                    &pf_fwd_adj_kernel<R, Model, W, P, false>)) == hipSuccess)
+    n = std::max(n, fa.sharedSizeBytes);
+  return n;
+}
+
 template <typename R, class Model, int W, int P>
 void add_entry(std::vector<PFKernel> &v, int model, int precision) {
-  constexpr int MP = W * 64 * P;
-  constexpr size_t stat = MP * (sizeof(double) + 3 * sizeof(R)) +
-                          (2 * (2 * W + 2) + 2 * W * Model::NP) * sizeof(double) + 4 * W + 64;
   v.push_back(PFKernel{model, Model::DX, precision, W, P, &launch_pf<R, Model, W, P>,
-                       &occupancy_pf<R, Model, W, P>, &dyn_lds_pf<R, Model, W, P>, stat});
+                       &occupancy_pf<R, Model, W, P>, &dyn_lds_pf<R, Model, W, P>,
+                       &static_lds_pf<R, Model, W, P>});
 }
 
 // Every d=1 launch shape for one (R, Model).
@@ -93,6 +108,7 @@ void add_all_tiles_16d(std::vector<PFKernel> &v, int model, int precision) {
   add_entry<R, Model, 4, 1>(v, model, precision);
   add_entry<R, Model, 4, 2>(v, model, precision);
   add_entry<R, Model, 8, 2>(v, model, precision);
+  add_entry<R, Model, 8, 4>(v, model, precision);
   add_entry<R, Model, 16, 2>(v, model, precision);
 }
 

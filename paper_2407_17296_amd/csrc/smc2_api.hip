@@ -151,7 +151,7 @@ int default_tile(int MP, int dx, int precision) {
       case 256: return 4;    // {4, 1}
       case 512: return 7;    // {4, 2}
       case 1024: return 11;  // {8, 2}
-      case 2048: return 17;  // {16, 2}
+      case 2048: return 14;  // {8, 4}: two waves per SIMD with a 256-register budget
     }
     return -1;
   }
@@ -284,6 +284,10 @@ smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, in
   L.seg = o->want_grad ? al((size_t)L.slots * L.c * (2 * dx + 1) * L.MP * rs) : 256;
   L.noise = (o->want_grad && o->store_noise)
                 ? al((size_t)L.slots * (Tc + 1) * dx * L.MP * rs) : 256;
+  // a filter's checkpoint and noise regions are addressed with 32-bit byte offsets
+  if ((size_t)L.nseg * (dx + 1) * L.MP * rs >= ((size_t)1 << 32) ||
+      (size_t)(Tc + 1) * dx * L.MP * rs >= ((size_t)1 << 32))
+    return fail(SMC2_E_UNSUPPORTED, "one filter's checkpoints or noise exceed 4 GiB");
   L.steps = al((size_t)L.slots * Tc * 8);
   L.stepscr = al((size_t)L.slots * 2 * Tc * 8);
   L.outer = al((size_t)items * (2 * m->D + 2) * 8);
@@ -376,7 +380,7 @@ smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_
     const int tile = resolve_tile(model, opts, M);
     const PFKernel *k = find_kernel(model->kind, opts->precision, tile);
     if (!k) return fail(SMC2_E_UNSUPPORTED, "kernel not built for this model / precision / tile");
-    if (k->static_lds + k->dyn_lds(std::max(T_max, 1)) > kMaxLdsBytes)
+    if (k->static_lds() + k->dyn_lds(std::max(T_max, 1)) > kMaxLdsBytes)
       return fail(SMC2_E_UNSUPPORTED, "T_max too long to stage the series in LDS");
   }
   ctx->T_max_hint = T_max;
