@@ -10,8 +10,9 @@ the timed iterations with inputs resident in HBM.
 
 Printed: one JSON line with the metric, the plain-FP64 form on the same workload, the same
 workload with the checkpoint interval held at ceil(sqrt(T_max)), the mixed and FP64 forms on the
-1-D linear-Gaussian workload (T = 250, N = 1024, M = 1024) and on the growth-model workload
-(T = 100, N = 4096, M = 512), the roofline of the dominant kernel (the fused filter, timed with
+1-D linear-Gaussian workload (T = 250, N = 1024, M = 1024), on the growth-model workload
+(T = 100, N = 4096, M = 512) and on the 16-dimensional linear-Gaussian workload (T = 100,
+N = 512, M = 2048), the roofline of the dominant kernel (the fused filter, timed with
 HIP events on its own stream) and the FP64 CPU oracle timed on a bounded sample on the host's
 cores.
 """
@@ -321,11 +322,12 @@ def main():
                          "M=1024, 2 16-dim LG, 3 growth, 4 SV (64 series, the default), 5 SIR")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-others", action="store_true",
-                    help="skip the 1-D LG and growth workloads' mixed and FP64 lines")
+                    help="skip the 1-D LG, growth and 16-dim LG workloads' mixed and FP64 "
+                         "lines")
     ap.add_argument("--no-sqrt", action="store_true",
                     help="skip the line with the checkpoint interval held at ceil(sqrt(T))")
     ap.add_argument("--other-steps", type=int, default=20,
-                    help="timed iterations per form on the 1-D LG and growth workloads")
+                    help="timed iterations per form on the other workloads")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -384,7 +386,7 @@ def main():
         res["mixed_over_fp64"] = mixed["value"] / fp64["value"]
         print("[bench] fp64: %.3f ms/iteration" % fp64["ms_per_step"], file=sys.stderr, flush=True)
     if not args.no_others:
-        for key, idx in (("lg1d_workload", 1), ("growth_workload", 3)):
+        for key, idx in (("lg1d_workload", 1), ("growth_workload", 3), ("lgdiag16_workload", 2)):
             if idx != args.workload:
                 res[key] = other_workload(idx, args.other_steps, 3, tune)
 

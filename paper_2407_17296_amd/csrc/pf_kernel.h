@@ -352,10 +352,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
   const size_t LD = (size_t)A.ld;
 
   for (int round = 0;; ++round) {
-    // the lane's first slot, opaque once per item: what is formed from it (noise counters and
-    // their first Philox products, addresses) is formed within the item, not held across items
-    int j0 = tid * PPL;
-    asm volatile("" : "+v"(j0));
+    // the lane's first slot, from a thread index made opaque once per item: what is formed from
+    // it (noise counters and their first Philox products, addresses) is formed within the item,
+    // not held across items; the mask and the multiple keep its range and alignment known
+    int to = tid;
+    asm volatile("" : "+v"(to));
+    const int j0 = (to & (NT - 1)) * PPL;
     int idx;
     __syncthreads();  // the previous item is done with every shared array
     if (A.persistent) {
