@@ -49,6 +49,12 @@ struct Bootstrap {
   // values of theta the model keeps in LDS (one copy per workgroup) instead of registers
   static constexpr int kShared = 0;
   __device__ void bind_shared(R *) {}
+  // values of each step that depend on t alone, tabulated once per filter in LDS (kPerStep per
+  // step; step_values(t, v) gives those of step t, and the model reads them back from the table
+  // bound before the first step)
+  static constexpr int kPerStep = 0;
+  __device__ static void step_values(int, R *) {}
+  __device__ void bind_steps(const R *) {}
   __device__ R advance(R *x, const R *e, const R *y) const {
     const Derived &m = *static_cast<const Derived *>(this);
     m.step(x, e);
@@ -228,6 +234,7 @@ template <typename R>
 struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
   static constexpr int DX = 1, DY = 1, NP = 2;
   R sx, c0, isy, drive, isx;  // c0 = -log(2 pi)/2 - log sy
+  const R *dtab;                // the forcing of steps 1..T (LDS)
   __device__ void setup(const double *th, const double *) {
     sx = (R)exp(th[0]);
     c0 = (R)(-kHalfLog2Pi - th[1]);
@@ -235,8 +242,11 @@ struct ModelGrowth : Bootstrap<ModelGrowth<R>, R> {
     isx = (R)exp(-th[0]);
     drive = (R)0;
   }
-  // the deterministic forcing of step t, evaluated once per step in FP64
-  __device__ void per_step(int t) { drive = (R)(8.0 * cos(1.2 * (double)t)); }
+  // the deterministic forcing of step t, evaluated in FP64 once per filter and step
+  static constexpr int kPerStep = 1;
+  __device__ static void step_values(int t, R *v) { v[0] = (R)(8.0 * cos(1.2 * (double)t)); }
+  __device__ void bind_steps(const R *tab) { dtab = tab; }
+  __device__ void per_step(int t) { drive = dtab[t - 1]; }
   __device__ void init(const R *e0, R *x) const { x[0] = e0[0]; }
   __device__ void init_adj(const R *, const R *, double *) const {}
   __device__ void step(R *x, const R *e) const {
@@ -317,8 +327,10 @@ struct ModelSV : Bootstrap<ModelSV<R>, R> {
 template <typename R>
 struct ModelLG1DOpt {
   static constexpr int DX = 1, DY = 1, NP = 3;
-  static constexpr int kShared = 0;  // as for the bootstrap models: nothing in LDS
+  static constexpr int kShared = 0, kPerStep = 0;  // as for the bootstrap models: no tables
   __device__ void bind_shared(R *) {}
+  __device__ static void step_values(int, R *) {}
+  __device__ void bind_steps(const R *) {}
   // kx = dm/dx = rho^2 a / sx^2, ky = rho^2 / sy^2, rx = rho^2 / sx^2, c0 = -log(2 pi)/2 -
   // log(s2)/2 and is2 = 1/s2 with s2 = sx^2 + sy^2, fx / fy = sx^2 / s2, sy^2 / s2
   R a, kx, ky, rx, rho, c0, is2, fx, fy, irho;

@@ -80,13 +80,14 @@ struct PFArgs {
   double mconst[4];     // model constants (the SIR model's N_pop, I_0, s_e^2, s_y)
 };
 
-// Dynamic shared memory of one item: y as R [lds_T * DY].  The per-step scalars (S_t, max_t and
-// the resampling flag), which one thread writes once per step and the adjoint reads once per
-// step, live in the slot's global scratch instead, so that a long series does not take LDS that
-// would otherwise hold more resident workgroups.
-template <typename R, int DY>
+// Dynamic shared memory of one item: y as R [lds_T * DY], then the model's per-step table as R
+// [lds_T * KS].  The per-step scalars (S_t, max_t and the resampling flag), which one thread
+// writes once per step and the adjoint reads once per step, live in the slot's global scratch
+// instead, so that a long series does not take LDS that would otherwise hold more resident
+// workgroups.
+template <typename R, int DY, int KS = 0>
 __host__ __device__ constexpr size_t pf_dyn_lds_bytes(int lds_T) {
-  return ((size_t)lds_T * DY * sizeof(R) + 7) / 8 * 8;
+  return ((size_t)lds_T * (DY + KS) * sizeof(R) + 7) / 8 * 8;
 }
 
 // The filter's noise (counter contract): element g = j*DX + q of step t (t = 0: the initial
@@ -394,6 +395,12 @@ void pf_fwd_adj_kernel(PFArgs A) {
     {
       const double *ys = A.y + (size_t)s * A.T_max * DY;
       for (int r = tid; r < T * DY; r += NT) sh_y[r] = (R)ys[r];
+    }
+    if constexpr (Model::kPerStep > 0) {  // the model's values of each step, once per filter
+      R *sh_st = sh_y + (size_t)A.lds_T * DY;
+      for (int r = tid; r < T; r += NT)
+        Model::step_values(r + 1, sh_st + (size_t)r * Model::kPerStep);
+      mdl.bind_steps(sh_st);
     }
 #pragma unroll
     for (int p = 0; p < PPL; ++p) sh_mark[j0 + p] = -1;

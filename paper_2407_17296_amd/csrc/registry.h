@@ -28,12 +28,12 @@ constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
 
 template <typename R, class Model, int W, int P>
 size_t dyn_lds_pf(int lds_T) {
-  return pf_dyn_lds_bytes<R, Model::DY>(lds_T);
+  return pf_dyn_lds_bytes<R, Model::DY, Model::kPerStep>(lds_T);
 }
 
 template <typename R, class Model, int W, int P>
 void launch_pf(const PFArgs &a, int grid, hipStream_t st) {
-  const size_t dyn = pf_dyn_lds_bytes<R, Model::DY>(a.lds_T);
+  const size_t dyn = pf_dyn_lds_bytes<R, Model::DY, Model::kPerStep>(a.lds_T);
   if (a.ckpt == 1)
     hipLaunchKernelGGL((pf_fwd_adj_kernel<R, Model, W, P, true>), dim3(grid), dim3(W * 64), dyn,
                        st, a);
