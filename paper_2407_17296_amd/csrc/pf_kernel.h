@@ -222,13 +222,15 @@ struct SysTargets {
     }
     return lo;
   }
-  // The estimate alone: floor(z) + 1, and whether z lies within kTieMargin of an integer (then
-  // upto must decide).
+  // The estimate alone: floor(z) + 1 clamped to [0, M], and whether z lies within kTieMargin of
+  // an integer (then upto must decide).  P = tot needs no case of its own: z is then M - nu to
+  // within a few ulp, so the estimate is M unless nu lies within the margin of 0 or 1, where the
+  // tie check hands it to upto.  (z >= -1 as P >= 0, and z <= M(1 + 2^-51), so the conversion
+  // is exact.)
   __device__ int estimate(double P, bool &near) const {
     const double z = fma(P, scale, -nu), fz = floor(z), fr = z - fz;
-    const int g = (int)fmin(fmax(fz + 1.0, 0.0), Md);
     near = near || !(fr > kTieMargin && fr < 1.0 - kTieMargin);
-    return P < tot ? g : M;
+    return min(max((int)fz + 1, 0), M);
   }
 };
 
@@ -252,8 +254,15 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     part += (double)ew[p];
-    const double P = (j0 + p == M - 1) ? tot : fmin(base + part, tot);
-    cm[p] = tg.estimate(P, near);
+    cm[p] = tg.estimate(fmin(base + part, tot), near);
+  }
+  // the last particle's prefix is the total: it owns the targets up to M (only the lane that
+  // holds it takes the branch)
+  const int lastp = M - 1 - j0;
+  if (lastp >= 0 && lastp < PPL) {
+#pragma unroll
+    for (int p = 0; p < PPL; ++p)
+      if (p == lastp) cm[p] = M;
   }
   if (near) {
     part = 0.0;
