@@ -991,6 +991,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
           load_row(T, xn);
           load_row(T - 1, xq);
         }
+        int gsel = 0;  // staging buffer of the next gather of parent states
         for (int t = T; t >= 1; --t) {
           win(t);
           const bool res_t = t < T && flag_of(t);
@@ -1016,12 +1017,16 @@ void pf_fwd_adj_kernel(PFArgs A) {
           if (res_p) {
 #pragma unroll
             for (int q = 0; q < DX; ++q) {
-              __syncthreads();  // earlier readers of the staging are done
+              // two staging buffers in turn (sh_lw, and the resampler's space, which the reverse
+              // sweep does not use): every wave passed the previous gather's barrier after its
+              // reads of the other buffer, so the buffer written now has no reader left
+              R *gs = gsel ? reinterpret_cast<R *>(sh_pm) : sh_lw;
+              gsel ^= 1;
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) sh_lw[j0 + p] = xq[p][q];
+              for (int p = 0; p < PPL; ++p) gs[j0 + p] = xq[p][q];
               __syncthreads();
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) xp[p][q] = sh_lw[pa[p]];
+              for (int p = 0; p < PPL; ++p) xp[p][q] = gs[pa[p]];
             }
           } else {
 #pragma unroll
