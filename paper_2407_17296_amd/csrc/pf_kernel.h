@@ -234,16 +234,6 @@ struct SysTargets {
   }
 };
 
-// Position of particle j in the workgroup's LDS staging arrays (gathers of parent states,
-// scatters to parents, the resampler's first-offspring markers): the PPL particles of a lane lie
-// NT words apart (row p holds particle p of every lane), so that the lanes' accesses to their
-// own particle p, and gathers through ancestors near the identity, fall on consecutive words,
-// one bank per lane, instead of PPL words apart.
-template <int NT, int PPL>
-__device__ __forceinline__ int stage_at(int j) {
-  return (int)(((unsigned)j % PPL) * NT + (unsigned)j / PPL);
-}
-
 // Ancestors of this thread's offspring slots under systematic resampling.  The weight prefix of
 // slot j0 + p is base + part_p (the exclusive prefix of the lane plus its running sum).  Each
 // parent marks the first offspring it owns, and an exclusive max-scan over the markers hands
@@ -287,16 +277,15 @@ __device__ __forceinline__ void systematic_ancestors(const SysTargets &tg, doubl
   for (int p = 0; p < PPL; ++p) {
     const int m = j0 + p;
     if (!FAST && m >= M) cm[p] = prev;
-    atomicMax(&sh_mark[cm[p] > prev ? stage_at<WAVES * 64, PPL>(prev) : dummy], m);
+    atomicMax(&sh_mark[cm[p] > prev ? prev : dummy], m);
     prev = max(prev, cm[p]);
   }
   __syncthreads();
   int run = -1;
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
-    const int at = stage_at<WAVES * 64, PPL>(j0 + p);
-    run = max(run, sh_mark[at]);
-    sh_mark[at] = -1;
+    run = max(run, sh_mark[j0 + p]);
+    sh_mark[j0 + p] = -1;
     a[p] = run;
   }
   const int before = block_exclusive_max_scan<WAVES>(run, sh_imax);
@@ -423,7 +412,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       mdl.bind_steps(sh_st);
     }
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) sh_mark[stage_at<NT, PPL>(j0 + p)] = -1;
+    for (int p = 0; p < PPL; ++p) sh_mark[j0 + p] = -1;
     R *ck = (R *)A.ckpt_buf + (size_t)slot * A.nseg_max * (DX + 1) * LD;
     int32_t *anc = A.anc + (size_t)slot * A.t_ld * LD;
     uint8_t *flg = A.flags + (size_t)slot * A.t_ld;
@@ -663,7 +652,7 @@ void pf_fwd_adj_kernel(PFArgs A) {
       const double base = off + dpp_f64<kDppWaveShr1>(0.0, inc);
       const double tot = S;
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) sx[stage_at<NT, PPL>(j0 + p)] = x[p][0];
+      for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][0];
       int a[PPL];
       if (systematic) {
         SysTargets tg;
@@ -703,15 +692,15 @@ void pf_fwd_adj_kernel(PFArgs A) {
       }
       // gather x through LDS (component 0 was staged above)
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) x[p][0] = sx[stage_at<NT, PPL>(a[p])];
+      for (int p = 0; p < PPL; ++p) x[p][0] = sx[a[p]];
 #pragma unroll
       for (int q = 1; q < DX; ++q) {
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) sx[stage_at<NT, PPL>(j0 + p)] = x[p][q];
+        for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][q];
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) x[p][q] = sx[stage_at<NT, PPL>(a[p])];
+        for (int p = 0; p < PPL; ++p) x[p][q] = sx[a[p]];
       }
       store_run<PPL>(anc + (size_t)(t - 1) * LD + j0, a);
 #pragma unroll
@@ -804,19 +793,18 @@ void pf_fwd_adj_kernel(PFArgs A) {
         for (int p = 0; p < PPL; ++p) {
           const R v = (j0 + p < M) ? xb[p][q] : (R)0;
           if (ca[p] != ra) {
-            if (rs != (R)0) atomicAdd(&ss[stage_at<NT, PPL>(ra)], rs);
+            if (rs != (R)0) atomicAdd(&ss[ra], rs);
             ra = ca[p];
             rs = (R)0;
           }
           rs += v;
         }
-        if (rs != (R)0) atomicAdd(&ss[stage_at<NT, PPL>(ra)], rs);
+        if (rs != (R)0) atomicAdd(&ss[ra], rs);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          const int at = stage_at<NT, PPL>(j0 + p);
-          xb[p][q] = ss[at];
-          ss[at] = (R)0;
+          xb[p][q] = ss[j0 + p];
+          ss[j0 + p] = (R)0;
         }
       }
     };
@@ -869,8 +857,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
       __syncthreads();  // earlier readers of the staging are done
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        sh_X[0][stage_at<NT, PPL>(j0 + p)] = (R)0;
-        sh_X[1][stage_at<NT, PPL>(j0 + p)] = (R)0;
+        sh_X[0][j0 + p] = (R)0;
+        sh_X[1][j0 + p] = (R)0;
       }
       __syncthreads();
       pp = 0;
@@ -1035,10 +1023,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
               R *gs = gsel ? reinterpret_cast<R *>(sh_pm) : sh_lw;
               gsel ^= 1;
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) gs[stage_at<NT, PPL>(j0 + p)] = xq[p][q];
+              for (int p = 0; p < PPL; ++p) gs[j0 + p] = xq[p][q];
               __syncthreads();
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) xp[p][q] = gs[stage_at<NT, PPL>(pa[p])];
+              for (int p = 0; p < PPL; ++p) xp[p][q] = gs[pa[p]];
             }
           } else {
 #pragma unroll
@@ -1150,10 +1138,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
               R *sx = sh_X[pp];
               pp ^= 1;
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) sx[stage_at<NT, PPL>(j0 + p)] = x[p][q];
+              for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][q];
               __syncthreads();
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) x[p][q] = sx[stage_at<NT, PPL>(a[p])];
+              for (int p = 0; p < PPL; ++p) x[p][q] = sx[a[p]];
             }
 #pragma unroll
             for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
