@@ -230,7 +230,9 @@ __device__ __forceinline__ int wave_id_opaque() {
 // LDS permutes: quad swaps and row mirrors for butterflies inside each row of 16 lanes, row
 // shifts and row broadcasts for scans.  Butterflies combine the same two operands in every lane
 // (addition is commutative), so each row ends with bit-identical values; the four row results
-// are then read as scalars and combined in a fixed order, so the wave result is uniform.  The
+// are then combined in a fixed order, either read as scalars or by two row broadcasts into lane
+// 63, which is then read, so the wave result is uniform.  Where the lanes a move leaves out take
+// the operation's identity, the move folds into the operation (one instruction per stage).  The
 // cross-wave stage reads the per-wave values in wave order, so the workgroup result is also
 // identical in every thread, which keeps data-dependent branches uniform.  Every lane of the
 // wave must be active.
@@ -293,13 +295,27 @@ __device__ __forceinline__ float readlane_f32(float v, int lane) {
 __device__ __forceinline__ float readlane_r(float v, int lane) { return readlane_f32(v, lane); }
 __device__ __forceinline__ double readlane_r(double v, int lane) { return readlane_f64(v, lane); }
 
+// The FP32 maximum of a wave, taken on order-preserving integer keys of the values (the bits,
+// with the magnitude bits of negative values flipped), which orders every non-NaN float as a
+// signed integer: an integer maximum takes its cross-lane operand straight from the DPP modifier,
+// where a floating-point one would first quiet it.  The row results are combined inside the
+// wave by row broadcasts, and lane 63 holds the maximum.
+__device__ __forceinline__ int fkey(float v) {
+  const int b = __float_as_int(v);
+  return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
 __device__ __forceinline__ float wave_max(float v) {
-  v = fmaxf(v, dpp_f32<kDppQuadXor1>(v));
-  v = fmaxf(v, dpp_f32<kDppQuadXor2>(v));
-  v = fmaxf(v, dpp_f32<kDppRowHalfMirror>(v));
-  v = fmaxf(v, dpp_f32<kDppRowMirror>(v));
-  return fmaxf(fmaxf(readlane_f32(v, 0), readlane_f32(v, 16)),
-               fmaxf(readlane_f32(v, 32), readlane_f32(v, 48)));
+  // the fill of lanes a move leaves out is INT_MIN, the identity of the maximum
+  constexpr int kLo = (int)0x80000000u;
+  int k = fkey(v);
+  k = max(k, __builtin_amdgcn_update_dpp(kLo, k, kDppQuadXor1, 0xF, 0xF, false));
+  k = max(k, __builtin_amdgcn_update_dpp(kLo, k, kDppQuadXor2, 0xF, 0xF, false));
+  k = max(k, __builtin_amdgcn_update_dpp(kLo, k, kDppRowHalfMirror, 0xF, 0xF, false));
+  k = max(k, __builtin_amdgcn_update_dpp(kLo, k, kDppRowMirror, 0xF, 0xF, false));
+  k = max(k, __builtin_amdgcn_update_dpp(kLo, k, kDppRowBcast15, 0xA, 0xF, false));
+  k = max(k, __builtin_amdgcn_update_dpp(kLo, k, kDppRowBcast31, 0xC, 0xF, false));
+  const int m = __builtin_amdgcn_readlane(k, 63);
+  return __int_as_float(m ^ ((m >> 31) & 0x7FFFFFFF));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -312,12 +328,24 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // The FP32 sum over a wave (the mixed form's sum of squared weights, which only decides whether
 // to resample).
+// The cross-lane operand with 0, the identity of the sum, where a move leaves a lane out, so that
+// the moves fold into the additions.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp0_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF,
+                                                    ROW_MASK == 0xF));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_f32<kDppQuadXor1>(v);
-  v += dpp_f32<kDppQuadXor2>(v);
-  v += dpp_f32<kDppRowHalfMirror>(v);
-  v += dpp_f32<kDppRowMirror>(v);
-  return (readlane_f32(v, 0) + readlane_f32(v, 16)) + (readlane_f32(v, 32) + readlane_f32(v, 48));
+  v += dpp0_f32<kDppQuadXor1>(v);
+  v += dpp0_f32<kDppQuadXor2>(v);
+  v += dpp0_f32<kDppRowHalfMirror>(v);
+  v += dpp0_f32<kDppRowMirror>(v);
+  // rows 1 and 3 add rows 0 and 2, then row 3 adds row 1: (r0 + r1) + (r2 + r3) in lane 63, the
+  // order of the four row sums as before
+  v += dpp0_f32<kDppRowBcast15, 0xA>(v);
+  v += dpp0_f32<kDppRowBcast31, 0xC>(v);
+  return readlane_f32(v, 63);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave (lane order).

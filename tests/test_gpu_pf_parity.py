@@ -95,15 +95,18 @@ def test_fp64_lg_diag16(oracle):
     _check_fp64(oracle, w, theta, ll, g, tr, k=2)
 
 
-@pytest.mark.parametrize("M,store_noise", [(256, 1), (256, 0), (2048, 1), (2048, 0)])
-def test_fp64_lg_diag16_every_step_checkpoints(oracle, M, store_noise):
-    """The 16-dimensional state with a checkpoint every step (the one-particle-at-a-time reverse
-    sweep the benchmark's launch shape uses for it), noise stored or regenerated, at 256
-    particles and at the largest filter (2048, sixteen waves), every item with its ancestry."""
+@pytest.mark.parametrize("M,store_noise,tile", [(256, 1, 0), (256, 0, 0), (2048, 1, 14),
+                                                (2048, 0, 14), (2048, 1, 17), (2048, 0, 17)])
+def test_fp64_lg_diag16_every_step_checkpoints(oracle, M, store_noise, tile):
+    """The 16-dimensional state with a checkpoint every step (the reverse sweep that streams
+    blocks of four components), noise stored or regenerated, at 256 particles and at the largest
+    filter, 2048 particles, on both shapes that hold it (eight waves x four particles per lane,
+    the default, and sixteen waves x two), every item with its ancestry."""
     w = synth.make(2, N=3, M=M, T=12)
     theta = spread_theta(w, 0.05, seed=60 + M + store_noise)
     items = [(0, i) for i in range(w.N)]
-    ll, g, tr = gpu_pf(w, theta, ckpt=1, k=2, store_noise=store_noise, trace_items=items)
+    ll, g, tr = gpu_pf(w, theta, tile=tile, ckpt=1, k=2, store_noise=store_noise,
+                       trace_items=items)
     _check_fp64(oracle, w, theta, ll, g, tr, k=2)
 
 
