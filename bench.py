@@ -362,6 +362,8 @@ def main():
           file=sys.stderr, flush=True)
     for a in mixed["tuned"].get("all", [])[:12]:
         print("[bench]   tuning: %s" % a, file=sys.stderr, flush=True)
+    for a in mixed["tuned"].get("refined", []):
+        print("[bench]   retimed: %s" % a, file=sys.stderr, flush=True)
 
     res = {}
     if not args.no_sqrt and force is None and tune:
