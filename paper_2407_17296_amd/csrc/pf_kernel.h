@@ -315,9 +315,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
   // the reverse sweep loads step t - 1 while step t is processed; a multi-dimensional state
   // loads each step where it is used instead (its registers are the limit there)
   constexpr bool kPrefetch = DX == 1;
-  // Wide states (a multiple of four components) stream one particle at a time through each
-  // step, so that a lane holds only its particles' states and adjoints across steps, and sum the
-  // parameter adjoint per wave into LDS instead of keeping NP FP64 accumulators per lane.
+  // Wide states (a multiple of four components) stream four components (one Philox block of the
+  // noise) of every particle of the lane at a time through each step, so that a lane holds only
+  // its particles' states and adjoints across steps, and sum the parameter adjoint per wave into
+  // LDS instead of keeping NP FP64 accumulators per lane.
   constexpr bool kWide = DX % 4 == 0;
   // With a checkpoint at every step (states of one or two components), row t of the checkpoints
   // holds the state after step t, before its resampling (row 0: x_0): the reverse sweep then has
@@ -870,11 +871,11 @@ void pf_fwd_adj_kernel(PFArgs A) {
       // its weight, and differentiates it.
       zero_staging();
       if constexpr (kWide) {
-        // one particle and four components at a time: the block's state before the step
-        // (checkpoint) and noise are read, the block's step rebuilt and differentiated.  The
+        // four components of every particle of the lane at a time: the block's state before the
+        // step (checkpoint) and noise are read, the block's step rebuilt and differentiated.  The
         // weight adjoint restarts from the normalised weights the forward stored.  The lane's
-        // parameter adjoint is summed in R over 16 steps at a time, then over the wave in FP64
-        // into its LDS row.
+        // parameter adjoint is summed in R over 16 steps at a time (the blocks' parts in LDS where
+        // they fit), then over the wave in FP64 into its LDS row.
         R tpl[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) tpl[k] = (R)0;
