@@ -284,9 +284,10 @@ smc2_status compute_layout(const smc2_model *m, const smc2_pf_opts *o, int S, in
   L.seg = o->want_grad ? al((size_t)L.slots * L.c * (2 * dx + 1) * L.MP * rs) : 256;
   L.noise = (o->want_grad && o->store_noise)
                 ? al((size_t)L.slots * (Tc + 1) * dx * L.MP * rs) : 256;
-  // a filter's checkpoint and noise regions are addressed with 32-bit byte offsets
+  // a filter's checkpoint and stored-noise regions are addressed with 32-bit byte offsets
+  const bool noise_stored = o->want_grad && o->store_noise;
   if ((size_t)L.nseg * (dx + 1) * L.MP * rs >= ((size_t)1 << 32) ||
-      (size_t)(Tc + 1) * dx * L.MP * rs >= ((size_t)1 << 32))
+      (noise_stored && (size_t)(Tc + 1) * dx * L.MP * rs >= ((size_t)1 << 32)))
     return fail(SMC2_E_UNSUPPORTED, "one filter's checkpoints or noise exceed 4 GiB");
   L.steps = al((size_t)L.slots * Tc * 8);
   L.stepscr = al((size_t)L.slots * 2 * Tc * 8);

@@ -80,6 +80,26 @@ def test_bad_options_and_sizes_are_rejected(lib):
         smc2.smc2_ctx_scratch_bytes(bad_prior, smc2.pf_opts(), 1, 1, 64, 10)
 
 
+def test_filter_regions_beyond_32_bit_offsets_are_refused(lib):
+    # a filter's stored noise is (T+1) x d x M_pow2 values: at d=16, M=2048 in FP64 that is
+    # 256 KiB per step, so 16383 steps reach 4 GiB and no longer fit 32-bit byte offsets
+    m = smc2.Model(smc2.LG_DIAG, 16, 18)
+    o = smc2.pf_opts(precision=smc2.FP64, ckpt_interval=0, store_noise=1)
+    assert smc2.smc2_ctx_scratch_bytes(m, o, 1, 1, 2048, 16382) > 0
+    with pytest.raises(smc2.SMC2Error) as e:
+        smc2.smc2_ctx_scratch_bytes(m, o, 1, 1, 2048, 16383)
+    assert e.value.status == smc2.SMC2_E_UNSUPPORTED
+    assert "4 GiB" in str(e.value)
+    # regenerating the noise stores none: the checkpoints (sqrt(T) rows) stay far below
+    o_regen = smc2.pf_opts(precision=smc2.FP64, ckpt_interval=0, store_noise=0)
+    assert smc2.smc2_ctx_scratch_bytes(m, o_regen, 1, 1, 2048, 16383) > 0
+    # a checkpoint at every step: (T+1) rows of (d+1) x M_pow2 values reach 4 GiB first
+    o_every = smc2.pf_opts(precision=smc2.FP64, ckpt_interval=1, store_noise=0)
+    assert smc2.smc2_ctx_scratch_bytes(m, o_every, 1, 1, 2048, 15419) > 0
+    with pytest.raises(smc2.SMC2Error):
+        smc2.smc2_ctx_scratch_bytes(m, o_every, 1, 1, 2048, 15420)
+
+
 def test_tile_table(lib):
     for t in range(1, 17):
         mp, w, p = smc2.smc2_tile_info(t, 1)
