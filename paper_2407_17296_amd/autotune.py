@@ -35,16 +35,19 @@ def _bucket(v):
 
 
 def kernel_sources_sha():
-    """Hash of the library's kernel sources: a cached choice made for other kernel code misses
-    the cache and is tuned again."""
+    """Hash of the code of the library's sources, comments and whitespace removed: a cached
+    choice made for other code misses the cache and is tuned again (an edited comment does not)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode())
-                h.update(fh.read())
+            with open(os.path.join(csrc, f)) as fh:
+                code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+            code = re.sub(r"//[^\n]*", " ", code)
+            h.update(f.encode())
+            h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

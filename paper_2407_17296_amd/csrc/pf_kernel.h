@@ -33,8 +33,9 @@
 // with a checkpoint at every step, one reverse sweep rebuilds each step from the state before it
 // and differentiates it; otherwise segments are processed last to first, each recomputed forward
 // from its checkpoint with the stored ancestors and stored s_t into a segment buffer, then swept
-// backward.  States of a multiple of four components go through the every-step sweep one
-// particle at a time, so that a lane keeps only its particles' adjoints across steps.  The
+// backward.  States of a multiple of four components go through the every-step sweep four
+// components (one Philox block of the noise) at a time, for every particle of the lane, so that a
+// lane keeps only its particles' states and adjoints across steps.  The
 // noise of the forward sweep is either stored by it (the reparameterisation draws it in
 // advance, eq. reparam_epsilon) and read back, or regenerated from the counter-based stream.
 // Because the normalised weights sum to one, the adjoint of the per-step log-weights between two
