@@ -25,6 +25,12 @@ __device__ __forceinline__ uint32_t stream_word(uint32_t k, uint32_t stream) {
   return (k << 8) | stream;
 }
 
+// a ^ b ^ c in one instruction: gfx950's three-input bitwise operation, whose 8-bit table is
+// indexed by the bits of (a, b, c) as (0xF0, 0xCC, 0xAA); 0xF0 ^ 0xCC ^ 0xAA = 0x96.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds; in each, words 0 and 2 are
 // multiplied (32x32 -> 64) by the two round multipliers, the high halves are mixed with words
 // 1 and 3 and the round key, and the key advances by the Weyl constants.
@@ -41,8 +47,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -75,8 +81,8 @@ __device__ __forceinline__ void philox4x32_10_n(const uint32_t (&c0)[NB], uint32
     for (int i = 0; i < NB; ++i) {
       const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)a[i];
       const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[i];
-      const uint32_t n0 = (uint32_t)(p1 >> 32) ^ b[i] ^ k0;
-      const uint32_t n2 = (uint32_t)(p0 >> 32) ^ d[i] ^ k1;
+      const uint32_t n0 = xor3((uint32_t)(p1 >> 32), b[i], k0);
+      const uint32_t n2 = xor3((uint32_t)(p0 >> 32), d[i], k1);
       b[i] = (uint32_t)p1;
       d[i] = (uint32_t)p0;
       a[i] = n0;

@@ -109,7 +109,11 @@ void add_all_tiles_16d(std::vector<PFKernel> &v, int model, int precision) {
   add_entry<R, Model, 4, 2>(v, model, precision);
   add_entry<R, Model, 8, 2>(v, model, precision);
   add_entry<R, Model, 8, 4>(v, model, precision);
-  add_entry<R, Model, 16, 2>(v, model, precision);
+  // sixteen waves x two particles per lane in FP32 only: in FP64 the state and its adjoint
+  // alone fill the 128 registers a lane has at four waves per SIMD, and that kernel (2 KB of
+  // spills per lane) returned gradients off the oracle once other kernels had run in the same
+  // process; the FP64 form runs 2048 particles on eight waves x four
+  if constexpr (sizeof(R) == 4) add_entry<R, Model, 16, 2>(v, model, precision);
 }
 
 // Launch shapes for the two-component state (SIR): one particle per lane or an even number.

@@ -28,14 +28,16 @@ U32 = 2.0 ** -24
 # Per-step gate on |s_t(mixed) - s_t(oracle)| while the ancestry agrees: the mixed form rounds
 # each particle's state, log-density and weight exponential to FP32, so a step's normaliser
 # carries an error of a few U32 times the magnitude of the log-weights it sums, plus the state's
-# rounding carried through the dynamics.  The linear-Gaussian and stochastic-volatility maps
-# contract (|a|, |phi| < 1 near the data-generating values), and the SIR map's compartments
+# rounding carried through the dynamics.  The linear-Gaussian maps (1-D and the diagonal
+# 16-dimensional one) and the stochastic-volatility map contract (|a|, |A_qq|, |phi| < 1 near
+# the data-generating values), and the SIR map's compartments
 # move by a few percent a day, so that rounding stays bounded: 256 U32 of the step's scale
 # 1 + |s_t|.  The growth map expands (its slope 1/2 + 25 (1 - x^2) /
 # (1 + x^2)^2 reaches 25.5 near x = 0), multiplying a state's rounding at every step a particle
 # passes there: 4096 U32.  The running log-likelihood must stay within the log-likelihood
 # tolerance 1e-4 T throughout.
-B_STEP_ULPS = {smc2.LG1D: 256.0, smc2.SV: 256.0, smc2.GROWTH: 4096.0, smc2.SIR: 256.0}
+B_STEP_ULPS = {smc2.LG1D: 256.0, smc2.LG_DIAG: 256.0, smc2.SV: 256.0, smc2.GROWTH: 4096.0,
+               smc2.SIR: 256.0}
 # Gradient gate of a filter whose ancestry never differs: the stated 1e-3 relative error.  The
 # growth map's gradient is ill-conditioned at FP32 resolution: perturbing theta by 2^-24
 # relative moves the FP64 oracle's own gradient by 1e-4 .. 1 relative on the filters near the
@@ -198,6 +200,19 @@ def test_mixed_against_oracle_in_the_benchmarked_configuration(oracle):
     items = [(s, i) for s in range(w.S) for i in (3, 200)]
     rows = _run(oracle, w, theta, 2, items, tile=3, ckpt=0, store_noise=1)
     _report_and_gate(oracle, w, theta, 2, rows, w.name)
+
+
+@pytest.mark.parametrize("tile", [14, 17])
+def test_mixed_against_oracle_lg_diag16(oracle, tile):
+    """The 16-dimensional LG workload at full size (T = 100, M = 2048) in its benchmarked
+    checkpoint schedule (every step, noise drawn again), on both shapes that hold 2048 particles
+    (eight waves x four particles per lane, and sixteen waves x two), every 21st of the 512
+    filters against the oracle."""
+    w = synth.make(2)
+    theta = spread_theta(w, 0.05, seed=66)
+    items = [(0, i) for i in range(0, w.N, 21)]
+    rows = _run(oracle, w, theta, 2, items, tile=tile, ckpt=1, store_noise=0)
+    _report_and_gate(oracle, w, theta, 2, rows, "%s tile %d" % (w.name, tile))
 
 
 def test_mixed_against_oracle_sir_outbreak(oracle):

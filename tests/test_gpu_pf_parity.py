@@ -96,18 +96,32 @@ def test_fp64_lg_diag16(oracle):
 
 
 @pytest.mark.parametrize("M,store_noise,tile", [(256, 1, 0), (256, 0, 0), (2048, 1, 14),
-                                                (2048, 0, 14), (2048, 1, 17), (2048, 0, 17)])
+                                                (2048, 0, 14)])
 def test_fp64_lg_diag16_every_step_checkpoints(oracle, M, store_noise, tile):
     """The 16-dimensional state with a checkpoint every step (the reverse sweep that streams
     blocks of four components), noise stored or regenerated, at 256 particles and at the largest
-    filter, 2048 particles, on both shapes that hold it (eight waves x four particles per lane,
-    the default, and sixteen waves x two), every item with its ancestry."""
+    filter, 2048 particles, on the FP64 shape that holds it (eight waves x four particles per
+    lane), every item with its ancestry."""
     w = synth.make(2, N=3, M=M, T=12)
     theta = spread_theta(w, 0.05, seed=60 + M + store_noise)
     items = [(0, i) for i in range(w.N)]
     ll, g, tr = gpu_pf(w, theta, tile=tile, ckpt=1, k=2, store_noise=store_noise,
                        trace_items=items)
     _check_fp64(oracle, w, theta, ll, g, tr, k=2)
+
+
+def test_fp64_lg_diag16_sixteen_waves_is_not_built():
+    """Sixteen waves x two particles per lane (tile 17) is built for the mixed form of the
+    16-dimensional state only: an FP64 reservation on it is refused as unsupported."""
+    w = synth.make(2, N=3, M=2048, T=12)
+    model = smc2.Model.from_workload(w)
+    with pytest.raises(smc2.SMC2Error) as e:
+        smc2.Context(model, smc2.pf_opts(precision=smc2.FP64, tile=17, ckpt_interval=1), w.S,
+                     w.N, w.M, w.T_len, w.T_max)
+    assert e.value.status == smc2.SMC2_E_UNSUPPORTED
+    ctx = smc2.Context(model, smc2.pf_opts(precision=smc2.MIXED, tile=17, ckpt_interval=1),
+                       w.S, w.N, w.M, w.T_len, w.T_max)
+    ctx.close()
 
 
 @pytest.mark.parametrize("index,kw,tile,ckpt,store_noise", [
