@@ -41,8 +41,8 @@ PEAK_VALU_TSLOTS = 256 * 128 * 2.4e9 / 1e12  # T FP32 lane-slots per second
 # transcendental unit (log, sqrt, sin, cos, exp) four (quarter rate).  The rates were measured
 # on the device with dependent-chain-free loops.
 #   noise      a Philox4x32-10 block serves 4 particles: 10 rounds x (2 multiply-adds x 4
-#              + 4 xors) / 4 = 30; half a Box-Muller pair: (8 full + 4 transcendental x 4)
-#              / 2 = 12                                                           -> 42
+#              + 2 three-input xors) / 4 = 25; half a Box-Muller pair: (8 full + 4
+#              transcendental x 4) / 2 = 12                                       -> 37
 #   model      the transition, log g, and the weight update with its NaN guard (3); per model
 #              below
 #   normalise  running max 1 (exact in FP32), subtract / scale / exp 6, FP64 conversion and
@@ -68,7 +68,7 @@ def alg_slots_per_particle_step(M, r, d=1, kind=0):
     derivatives scale with d (an estimate for the models without their own entry, exact in form
     only for the linear-Gaussian ones)."""
     fwd_model, adj_model = MODEL_SLOTS.get(kind, MODEL_SLOTS[0])
-    noise, model, normalise = 42.0 * d, fwd_model * d, 13.0
+    noise, model, normalise = 37.0 * d, fwd_model * d, 13.0
     forward = noise + model + normalise + 30.0 * r
     adjoint = adj_model * d + 3.0 + 2.0 * r * d
     return forward + adjoint
