@@ -59,8 +59,14 @@ PEAK_VALU_TSLOTS = 256 * 128 * 2.4e9 / 1e12  # T FP32 lane-slots per second
 #           the exp unit 5, two FMAs 2, update 3 -> 14; adjoint: d log g / dx with exp(-x)
 #           again 9 (y^2 / 2 1, exp 5, FMA 1, scale by the weight adjoint 1, add 1), the
 #           transition's (1 - phi) x_b 1, (1 - phi^2)(x - mu) x_b 3, s e x_b 2, phi x_b 1 -> 16
+#   growth  transition x/2 + 25 x / (1 + x^2) + forcing + sx e: 1 + x^2 1, the reciprocal 4,
+#           25 x and its product 2, x/2 + 1, sx e + forcing 1, sum 1 -> 10; log g: x^2 1,
+#           y - x^2/20 1, / sy 1, -r/2 * r + c 2 -> 5; update 3 -> 18; adjoint: d log g / dx and
+#           / d log sy with the residual rebuilt 3, wb r x / (10 sy^2) and its add 5, wb (r^2 - 1)
+#           and its add 3 -> 11; the transition's slope 1/2 + 25 (1 - x^2) / (1 + x^2)^2 with its
+#           reciprocal 9, sx e x_b and its add 3, x_b times the slope 1 -> 13; -> 24
 # Rebuilding the step in the adjoint (from checkpoints) is implementation work, not counted.
-MODEL_SLOTS = {0: (9.0, 11.0), 3: (14.0, 16.0)}
+MODEL_SLOTS = {0: (9.0, 11.0), 2: (18.0, 24.0), 3: (14.0, 16.0)}
 
 
 def alg_slots_per_particle_step(M, r, d=1, kind=0):
