@@ -133,7 +133,8 @@ smc2_status smc2_ctx_create(smc2_ctx **out, int device);
  * SMC2_E_INVALID_ARG.  scratch_budget_bytes = 0 means no limit beyond device memory; a larger
  * need returns SMC2_E_OUT_OF_MEMORY and allocates nothing.  T_len (host [S]) gives each series'
  * length, used to order work longest first.  SMC2_E_UNSUPPORTED when M is above the largest
- * built tile, when the series do not fit the kernel's LDS staging, or when one filter's
+ * built tile, when the requested tile is not built for the model and precision, when the series
+ * do not fit the kernel's LDS staging, or when one filter's
  * checkpoints or stored noise would take 4 GiB or more (they are addressed with 32-bit
  * offsets). */
 smc2_status smc2_ctx_reserve(smc2_ctx *ctx, const smc2_model *model, const smc2_pf_opts *opts,
@@ -303,7 +304,10 @@ smc2_status smc2_philox_probe(int32_t R, const uint32_t *ctr, const uint32_t *n,
                               float *uniforms32, void *stream);
 
 /* Launch shapes built into the library: for tile index t >= 1, the particles per workgroup,
- * waves per workgroup and particles per lane; returns SMC2_E_INVALID_ARG past the last. */
+ * waves per workgroup and particles per lane of a shape built for state dimension d_x in at least
+ * one precision; returns SMC2_E_INVALID_ARG past the last or for a shape not built for d_x.  A
+ * precision can lack a shape (the 16-dimensional FP64 form has no sixteen waves x two particles
+ * per lane), which smc2_ctx_reserve refuses with SMC2_E_UNSUPPORTED. */
 smc2_status smc2_tile_info(int32_t tile, int32_t d_x, int32_t *max_particles, int32_t *waves,
                            int32_t *per_lane);
 
