@@ -780,33 +780,52 @@ void pf_fwd_adj_kernel(PFArgs A) {
     for (int p = 0; p < NP; ++p) tb[p] = 0.0;
     if (kWide && lane == 0)
       for (int k = 0; k < NP; ++k) sh_tb[wid * NP + k] = 0.0;
-    int pp = 0;  // ping-pong selector of the gather / scatter staging in sh_X
+    int pp = 0;  // ping-pong selector of the gather / scatter staging
+    // The scatter stages SB components per barrier in one of two sets in turn: a set is one row
+    // of sh_X; for wide FP32 states (SB = 2) set 0 is both rows of sh_X and set 1 the
+    // resampler's space, which the reverse sweep does not otherwise use, as two rows of R.
+    constexpr int SB = (kWide && sizeof(R) == 4) ? 2 : 1;
+    auto stage_row = [&](int set, int i) -> R * {
+      if constexpr (SB == 1)
+        return sh_X[set];
+      else
+        return set == 0 ? sh_X[i] : reinterpret_cast<R *>(sh_pm) + (size_t)i * MP;
+    };
     // offspring -> parent: xb_pre[m] = sum over offspring i with a_i = m of xb_post[i]; a lane
     // adds each run of its offspring that share a parent once.  The staging is zero before use
-    // and each reader zeroes what it read.
+    // and each reader zeroes what it read; a set is written again only after the barrier of the
+    // other set, which every reader of its previous use has passed.
     auto scatter_to_parents = [&](const int (&ca)[PPL]) {
 #pragma unroll
-      for (int q = 0; q < DX; ++q) {
-        R *ss = sh_X[pp];
+      for (int q0 = 0; q0 < DX; q0 += SB) {
+        const int set = pp;
         pp ^= 1;
-        int ra = ca[0];
-        R rs = (R)0;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          const R v = (j0 + p < M) ? xb[p][q] : (R)0;
-          if (ca[p] != ra) {
-            if (rs != (R)0) atomicAdd(&ss[ra], rs);
-            ra = ca[p];
-            rs = (R)0;
+        for (int i = 0; i < SB; ++i) {
+          R *ss = stage_row(set, i);
+          int ra = ca[0];
+          R rs = (R)0;
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            const R v = (j0 + p < M) ? xb[p][q0 + i] : (R)0;
+            if (ca[p] != ra) {
+              if (rs != (R)0) atomicAdd(&ss[ra], rs);
+              ra = ca[p];
+              rs = (R)0;
+            }
+            rs += v;
           }
-          rs += v;
+          if (rs != (R)0) atomicAdd(&ss[ra], rs);
         }
-        if (rs != (R)0) atomicAdd(&ss[ra], rs);
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          xb[p][q] = ss[j0 + p];
-          ss[j0 + p] = (R)0;
+        for (int i = 0; i < SB; ++i) {
+          R *ss = stage_row(set, i);
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            xb[p][q0 + i] = ss[j0 + p];
+            ss[j0 + p] = (R)0;
+          }
         }
       }
     };
@@ -861,6 +880,10 @@ void pf_fwd_adj_kernel(PFArgs A) {
       for (int p = 0; p < PPL; ++p) {
         sh_X[0][j0 + p] = (R)0;
         sh_X[1][j0 + p] = (R)0;
+        if constexpr (SB == 2) {
+          stage_row(1, 0)[j0 + p] = (R)0;
+          stage_row(1, 1)[j0 + p] = (R)0;
+        }
       }
       __syncthreads();
       pp = 0;
