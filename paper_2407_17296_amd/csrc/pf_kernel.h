@@ -1018,87 +1018,96 @@ void pf_fwd_adj_kernel(PFArgs A) {
           load_row(T - 1, xq);
         }
         int gsel = 0;  // staging buffer of the next gather of parent states
-        for (int t = T; t >= 1; --t) {
-          win(t);
-          const bool res_t = t < T && flag_of(t);
-          const bool res_p = t > 1 && flag_of(t - 1);  // resampled after step t - 1
-          const bool need_w = t == T || res_t;
-          // the carry into step t, stored where the weights are rebuilt and not uniform
-          R cl[PPL];
-          if (need_w && t > 1 && !res_p)
-            load_run<PPL>(ck + (size_t)(t - 1) * (DX + 1) * LD + DX * LD + j0, cl);
-          else
+        // with and without the stored noise as two loops: a load of the noise under a branch in
+        // the loop made every step wait for all of its loads (the prefetched row included)
+        // before recovering the noise on the other path
+        auto sweep = [&](auto stored) {
+          for (int t = T; t >= 1; --t) {
+            win(t);
+            const bool res_t = t < T && flag_of(t);
+            const bool res_p = t > 1 && flag_of(t - 1);  // resampled after step t - 1
+            const bool need_w = t == T || res_t;
+            // the carry into step t, stored where the weights are rebuilt and not uniform
+            R cl[PPL];
+            if (need_w && t > 1 && !res_p)
+              load_run<PPL>(ck + (size_t)(t - 1) * (DX + 1) * LD + DX * LD + j0, cl);
+            else
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) cl[p] = lWeqR;
-          int pa[PPL];
-          if (res_p)
-            load_run<PPL>(anc + (size_t)(t - 2) * LD + j0, pa);
-          else
+              for (int p = 0; p < PPL; ++p) cl[p] = lWeqR;
+            int pa[PPL];
+            if (res_p)
+              load_run<PPL>(anc + (size_t)(t - 2) * LD + j0, pa);
+            else
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) pa[p] = 0;
-          R xq2[PPL][DX];  // the state after step t - 2, for the next step
-          if (t >= 2) load_row(t - 2, xq2);
-          // the state before step t
-          R xp[PPL][DX];
-          if (res_p) {
+              for (int p = 0; p < PPL; ++p) pa[p] = 0;
+            R xq2[PPL][DX];  // the state after step t - 2, for the next step
+            if (t >= 2) load_row(t - 2, xq2);
+            // the state before step t
+            R xp[PPL][DX];
+            if (res_p) {
 #pragma unroll
-            for (int q = 0; q < DX; ++q) {
-              // two staging buffers in turn (sh_lw, and the resampler's space, which the reverse
-              // sweep does not use): every wave passed the previous gather's barrier after its
-              // reads of the other buffer, so the buffer written now has no reader left
-              R *gs = gsel ? reinterpret_cast<R *>(sh_pm) : sh_lw;
-              gsel ^= 1;
+              for (int q = 0; q < DX; ++q) {
+                // two staging buffers in turn (sh_lw, and the resampler's space, which the reverse
+                // sweep does not use): every wave passed the previous gather's barrier after its
+                // reads of the other buffer, so the buffer written now has no reader left
+                R *gs = gsel ? reinterpret_cast<R *>(sh_pm) : sh_lw;
+                gsel ^= 1;
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) gs[j0 + p] = xq[p][q];
-              __syncthreads();
+                for (int p = 0; p < PPL; ++p) gs[j0 + p] = xq[p][q];
+                __syncthreads();
 #pragma unroll
-              for (int p = 0; p < PPL; ++p) xp[p][q] = gs[pa[p]];
+                for (int p = 0; p < PPL; ++p) xp[p][q] = gs[pa[p]];
+              }
+            } else {
+#pragma unroll
+              for (int p = 0; p < PPL; ++p)
+#pragma unroll
+                for (int q = 0; q < DX; ++q) xp[p][q] = xq[p][q];
             }
-          } else {
+            mdl.per_step(t);
+            const R *yv = sh_y + (size_t)(t - 1) * DY;
+            // the step's noise: read back where the forward stored it, else recovered
+            R ce[PPL][DX];
+            if constexpr (decltype(stored)::value) {
 #pragma unroll
-            for (int p = 0; p < PPL; ++p)
+              for (int q = 0; q < DX; ++q)
+                load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ce, q);
+            } else {
 #pragma unroll
-              for (int q = 0; q < DX; ++q) xp[p][q] = xq[p][q];
-          }
-          mdl.per_step(t);
-          const R *yv = sh_y + (size_t)(t - 1) * DY;
-          // the step's noise: read back where the forward stored it, else recovered
-          R ce[PPL][DX];
-          if (nz) {
+              for (int p = 0; p < PPL; ++p) mdl.noise_of(xp[p], xn[p], yv, ce[p]);
+            }
+            // the weight adjoint restarts from the step's normalised weights
+            if (need_w) {
+              const R st = st_of(t);  // max_t + log S_t
 #pragma unroll
-            for (int q = 0; q < DX; ++q)
-              load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ce, q);
-          } else {
+              for (int p = 0; p < PPL; ++p) {
+                R v = cl[p] + mdl.weight_of(yv, xp[p], xn[p]);
+                if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
+                wb[p] = fexp(v - st);
+              }
+            }
+            if (res_t) scatter_to_parents(ca);
+            R tp[NP];
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) mdl.noise_of(xp[p], xn[p], yv, ce[p]);
-          }
-          // the weight adjoint restarts from the step's normalised weights
-          if (need_w) {
-            const R st = st_of(t);  // max_t + log S_t
+            for (int k = 0; k < NP; ++k) tp[k] = (R)0;
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) mdl.advance_adj(yv, xp[p], xn[p], ce[p], wb[p], xb[p], tp);
+            add_step_adjoint(tp);
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
-              R v = cl[p] + mdl.weight_of(yv, xp[p], xn[p]);
-              if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
-              wb[p] = fexp(v - st);
+              ca[p] = pa[p];
+#pragma unroll
+              for (int q = 0; q < DX; ++q) {
+                xn[p][q] = xq[p][q];
+                xq[p][q] = xq2[p][q];
+              }
             }
           }
-          if (res_t) scatter_to_parents(ca);
-          R tp[NP];
-#pragma unroll
-          for (int k = 0; k < NP; ++k) tp[k] = (R)0;
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) mdl.advance_adj(yv, xp[p], xn[p], ce[p], wb[p], xb[p], tp);
-          add_step_adjoint(tp);
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) {
-            ca[p] = pa[p];
-#pragma unroll
-            for (int q = 0; q < DX; ++q) {
-              xn[p][q] = xq[p][q];
-              xq[p][q] = xq2[p][q];
-            }
-          }
-        }
+        };
+        if (nz)
+          sweep(std::true_type{});
+        else
+          sweep(std::false_type{});
       }
     } else {
       // segment rows of one step: x before the step (DX rows), the noise when it is not
