@@ -1028,18 +1028,27 @@ void pf_fwd_adj_kernel(PFArgs A) {
             const bool res_p = t > 1 && flag_of(t - 1);  // resampled after step t - 1
             const bool need_w = t == T || res_t;
             // the carry into step t, stored where the weights are rebuilt and not uniform
+            // (each conditional load is waited for on its own path, before the next row's load
+            // is issued: its registers, reused later on the other path, would otherwise make
+            // that write wait for every load in flight)
             R cl[PPL];
-            if (need_w && t > 1 && !res_p)
+            if (need_w && t > 1 && !res_p) {
               load_run<PPL>(ck + (size_t)(t - 1) * (DX + 1) * LD + DX * LD + j0, cl);
-            else
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) asm volatile("" : "+v"(cl[p]));
+            } else {
 #pragma unroll
               for (int p = 0; p < PPL; ++p) cl[p] = lWeqR;
+            }
             int pa[PPL];
-            if (res_p)
+            if (res_p) {
               load_run<PPL>(anc + (size_t)(t - 2) * LD + j0, pa);
-            else
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) asm volatile("" : "+v"(pa[p]));
+            } else {
 #pragma unroll
               for (int p = 0; p < PPL; ++p) pa[p] = 0;
+            }
             R xq2[PPL][DX];  // the state after step t - 2, for the next step
             if (t >= 2) load_row(t - 2, xq2);
             // the state before step t
