@@ -1100,7 +1100,8 @@ void pf_fwd_adj_kernel(PFArgs A) {
 #pragma unroll
             for (int k = 0; k < NP; ++k) tp[k] = (R)0;
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) mdl.advance_adj(yv, xp[p], xn[p], ce[p], wb[p], xb[p], tp);
+            for (int p = 0; p < PPL; ++p)
+              mdl.advance_adj(yv, xp[p], xn[p], ce[p], wb[p], xb[p], tp);
             add_step_adjoint(tp);
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
@@ -1125,120 +1126,138 @@ void pf_fwd_adj_kernel(PFArgs A) {
       const int WROW = ROW - 1;
       R *sg = (R *)A.seg_buf + (size_t)slot * c * (2 * DX + 1) * LD;
       const int nseg = (T + c - 1) / c;
-      for (int seg = nseg - 1; seg >= 0; --seg) {
-        const int t0 = seg * c, t1 = min(T, t0 + c);
-        const R *cks = ck + (size_t)seg * (DX + 1) * LD;
+      // with and without the stored noise as two loops (as in the every-step sweep)
+      auto seg_sweep = [&](auto stored) {
+        for (int seg = nseg - 1; seg >= 0; --seg) {
+          const int t0 = seg * c, t1 = min(T, t0 + c);
+          const R *cks = ck + (size_t)seg * (DX + 1) * LD;
 #pragma unroll
-        for (int q = 0; q < DX; ++q) load_comp<PPL>(cks + q * LD + j0, x, q);
-        if (t0 > 0) win(t0);
-        if (kWide || (t0 > 0 && !flag_of(t0)))
-          load_run<PPL>(cks + DX * LD + j0, lW);
-        else
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
-        // recompute the segment with the stored ancestors and log normalisers
-        R ne[PPL][DX];
-        if (nz) load_noise(t0 + 1, ne);
-        for (int t = t0 + 1; t <= t1; ++t) {
-          win(t);
-          const bool res = flag_of(t);
-          int a[PPL];
-          if (res) load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, a);
-          R e[PPL][DX];
-          if (nz) {
-#pragma unroll
-            for (int p = 0; p < PPL; ++p)
-#pragma unroll
-              for (int q = 0; q < DX; ++q) e[p][q] = ne[p][q];
-            if (t < t1) load_noise(t + 1, ne);
-          } else {
-            filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
-          }
-          mdl.per_step(t);
-          const R *yv = sh_y + (size_t)(t - 1) * DY;
-          R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
-          const R st = st_of(t), mt = mt_of(t);  // max_t + log S_t, max_t
-          R wv[PPL];
-#pragma unroll
-          for (int q = 0; q < DX; ++q) {
-            store_comp<PPL>(row + q * LD + j0, x, q);
-            if (!nz) store_comp<PPL>(row + (DX + q) * LD + j0, e, q);
-          }
-#pragma unroll
-          for (int p = 0; p < PPL; ++p) {
-            R v = lW[p] + mdl.advance(x[p], e[p], yv);
-            if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
-            wv[p] = v;
-            lW[p] = v - mt;
-          }
-          if (t == T || res) {
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) wv[p] = fexp(wv[p] - st);
-            store_run<PPL>(row + WROW * LD + j0, wv);
-          }
-          if (res) {
-#pragma unroll
-            for (int q = 0; q < DX; ++q) {
-              R *sx = sh_X[pp];
-              pp ^= 1;
-#pragma unroll
-              for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][q];
-              __syncthreads();
-#pragma unroll
-              for (int p = 0; p < PPL; ++p) x[p][q] = sx[a[p]];
-            }
+          for (int q = 0; q < DX; ++q) load_comp<PPL>(cks + q * LD + j0, x, q);
+          if (t0 > 0) win(t0);
+          if (kWide || (t0 > 0 && !flag_of(t0)))
+            load_run<PPL>(cks + DX * LD + j0, lW);
+          else
 #pragma unroll
             for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
-          }
-        }
-        zero_staging();
-        // reverse sweep over the segment; the rows (state before the step, noise, weight) and
-        // ancestors of step t - 1 are loaded while step t is processed
-        R nx[PPL][DX], nw[PPL];
-        int na[PPL];
-        // reads the flag of step t from the window of step t or t + 1
-        auto load_step = [&](int t) {
-          const R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
-          const bool lres = t < T && flag_of(t);
-#pragma unroll
-          for (int q = 0; q < DX; ++q) {
-            load_comp<PPL>(row + q * LD + j0, nx, q);
-            load_comp<PPL>(nz ? nz + ((size_t)t * DX + q) * LD + j0 : row + (DX + q) * LD + j0,
-                           ne, q);
-          }
-          if (t == T || lres)
-            load_run<PPL>(row + WROW * LD + j0, nw);
-          else
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) nw[p] = (R)0;
-          if (lres)
-            load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, na);
-          else
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) na[p] = 0;
-        };
-        win(t1);
-        if (kPrefetch) load_step(t1);
-        for (int t = t1; t > t0; --t) {
-          R cx[PPL][DX], ce[PPL][DX], cw[PPL];
-          int ca[PPL];
-          win(t);
-          if (!kPrefetch) load_step(t);
+          // the checkpoint is waited for here: state registers still loading on entry to the
+          // loop below would make every step of it wait for all of its loads and stores
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
+            asm volatile("" : "+v"(lW[p]));
+#pragma unroll
+            for (int q = 0; q < DX; ++q) asm volatile("" : "+v"(x[p][q]));
+          }
+          // recompute the segment with the stored ancestors and log normalisers
+          R ne[PPL][DX];
+          if constexpr (decltype(stored)::value) load_noise(t0 + 1, ne);
+          for (int t = t0 + 1; t <= t1; ++t) {
+            win(t);
+            const bool res = flag_of(t);
+            int a[PPL];
+            if (res) load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, a);
+            R e[PPL][DX];
+            if constexpr (decltype(stored)::value) {
+#pragma unroll
+              for (int p = 0; p < PPL; ++p)
+#pragma unroll
+                for (int q = 0; q < DX; ++q) e[p][q] = ne[p][q];
+              if (t < t1) load_noise(t + 1, ne);
+            } else {
+              filter_noise<R, DX, PPL>(j0, fid, c3s, (uint32_t)t, seed, e);
+            }
+            mdl.per_step(t);
+            const R *yv = sh_y + (size_t)(t - 1) * DY;
+            R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
+            const R st = st_of(t), mt = mt_of(t);  // max_t + log S_t, max_t
+            R wv[PPL];
 #pragma unroll
             for (int q = 0; q < DX; ++q) {
-              cx[p][q] = nx[p][q];
-              ce[p][q] = ne[p][q];
+              store_comp<PPL>(row + q * LD + j0, x, q);
+              if constexpr (!decltype(stored)::value)
+                store_comp<PPL>(row + (DX + q) * LD + j0, e, q);
             }
-            cw[p] = nw[p];
-            ca[p] = na[p];
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+              R v = lW[p] + mdl.advance(x[p], e[p], yv);
+              if (!(v == v) || j0 + p >= M) v = (R)kNegInf;
+              wv[p] = v;
+              lW[p] = v - mt;
+            }
+            if (t == T || res) {
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) wv[p] = fexp(wv[p] - st);
+              store_run<PPL>(row + WROW * LD + j0, wv);
+            }
+            if (res) {
+#pragma unroll
+              for (int q = 0; q < DX; ++q) {
+                R *sx = sh_X[pp];
+                pp ^= 1;
+#pragma unroll
+                for (int p = 0; p < PPL; ++p) sx[j0 + p] = x[p][q];
+                __syncthreads();
+#pragma unroll
+                for (int p = 0; p < PPL; ++p) x[p][q] = sx[a[p]];
+              }
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) lW[p] = lWeqR;
+            }
           }
-          if (kPrefetch && t - 1 > t0) load_step(t - 1);
-          mdl.per_step(t);
-          reverse_step(t, cx, ce, cw, ca);
+          zero_staging();
+          // reverse sweep over the segment; the rows (state before the step, noise, weight) and
+          // ancestors of step t - 1 are loaded while step t is processed
+          R nx[PPL][DX], nw[PPL];
+          int na[PPL];
+          // reads the flag of step t from the window of step t or t + 1
+          auto load_step = [&](int t) {
+            const R *row = sg + (size_t)(t - t0 - 1) * ROW * LD;
+            const bool lres = t < T && flag_of(t);
+#pragma unroll
+            for (int q = 0; q < DX; ++q) {
+              load_comp<PPL>(row + q * LD + j0, nx, q);
+              if constexpr (decltype(stored)::value)
+                load_comp<PPL>(nz + ((size_t)t * DX + q) * LD + j0, ne, q);
+              else
+                load_comp<PPL>(row + (DX + q) * LD + j0, ne, q);
+            }
+            if (t == T || lres)
+              load_run<PPL>(row + WROW * LD + j0, nw);
+            else
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) nw[p] = (R)0;
+            if (lres)
+              load_run<PPL>(anc + (size_t)(t - 1) * LD + j0, na);
+            else
+#pragma unroll
+              for (int p = 0; p < PPL; ++p) na[p] = 0;
+          };
+          win(t1);
+          if (kPrefetch) load_step(t1);
+          for (int t = t1; t > t0; --t) {
+            R cx[PPL][DX], ce[PPL][DX], cw[PPL];
+            int ca[PPL];
+            win(t);
+            if (!kPrefetch) load_step(t);
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+#pragma unroll
+              for (int q = 0; q < DX; ++q) {
+                cx[p][q] = nx[p][q];
+                ce[p][q] = ne[p][q];
+              }
+              cw[p] = nw[p];
+              ca[p] = na[p];
+            }
+            if (kPrefetch && t - 1 > t0) load_step(t - 1);
+            mdl.per_step(t);
+            reverse_step(t, cx, ce, cw, ca);
+          }
         }
-      }
+      };
+      if (nz)
+        seg_sweep(std::true_type{});
+      else
+        seg_sweep(std::false_type{});
     }
     {
       R e[PPL][DX];
